@@ -1,0 +1,150 @@
+"""FP64 CPU oracle for the binned BLS periodogram -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never imports it and it
+never imports the GPU library; the two share no code.
+
+The arithmetic lives in ``bls_oracle.c`` (plain C, FP64, no fast math), which
+states the method (Law et al. 2011, section 2.2.2, and the box-least-squares
+statistic it cites) and every reading of it.  This module only builds that
+file with gcc and marshals numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bls_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_bls.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Prep(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("t0", ctypes.c_double),
+                ("W", ctypes.c_double), ("xbar", ctypes.c_double),
+                ("sumwy2", ctypes.c_double), ("kmin", ctypes.c_int32),
+                ("kmax", ctypes.c_int32)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    lib.bls_oracle_search.argtypes = [
+        P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32,
+        ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+        ctypes.c_int32, P, P, P, P, P, P]
+    lib.bls_oracle_search.restype = ctypes.c_int
+    lib.bls_oracle_bins.argtypes = [
+        P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P, P, P, P]
+    lib.bls_oracle_bins.restype = ctypes.c_int64
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(ValueError):
+    pass
+
+
+@dataclass
+class OracleResult:
+    sr: np.ndarray         # [nperiods] float64
+    depth: np.ndarray      # [nperiods] float64 (NaN where no box)
+    jstart: np.ndarray     # [nperiods] int32 (-1 where no box)
+    kwidth: np.ndarray     # [nperiods] int32 (-1 where no box)
+    best_index: int
+    n: int
+    t0: float
+    W: float
+    xbar: float
+    sumwy2: float
+    kmin: int
+    kmax: int
+
+    def phase(self, nbins: int) -> np.ndarray:
+        out = self.jstart / float(nbins)
+        return np.where(self.jstart < 0, np.nan, out)
+
+    def duration(self, periods, nbins: int) -> np.ndarray:
+        out = self.kwidth * np.asarray(periods, np.float64) / float(nbins)
+        return np.where(self.kwidth < 0, np.nan, out)
+
+
+def search(t, x, w, periods, nbins, qmin, qmax, *, min_in_points=1,
+           dip_only=False, nthreads=0) -> OracleResult:
+    """Periodogram of one light curve (see bls_oracle.c for the definition)."""
+    lib = _load()
+    t = _f64(t)
+    x = _f64(x)
+    w = None if w is None else _f64(w)
+    periods = _f64(periods)
+    n = t.shape[0]
+    if x.shape[0] != n or (w is not None and w.shape[0] != n):
+        raise OracleError("length mismatch")
+    m = periods.shape[0]
+    sr = np.empty(m, np.float64)
+    depth = np.empty(m, np.float64)
+    js = np.empty(m, np.int32)
+    ks = np.empty(m, np.int32)
+    best = ctypes.c_int64(-1)
+    prep = _Prep()
+    st = lib.bls_oracle_search(
+        _ptr(t), _ptr(x), _ptr(w), n, _ptr(periods), m, int(nbins),
+        float(qmin), float(qmax), int(min_in_points), int(bool(dip_only)),
+        int(nthreads), _ptr(sr), _ptr(depth), _ptr(js), _ptr(ks),
+        ctypes.byref(best), ctypes.byref(prep))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    return OracleResult(sr, depth, js, ks, int(best.value), int(prep.n),
+                        prep.t0, prep.W, prep.xbar, prep.sumwy2,
+                        int(prep.kmin), int(prep.kmax))
+
+
+def bins(t, x, w, period, nbins):
+    """Bin index of every kept point, and the per-bin sums, at one period.
+
+    Returns (bins[int32, n_kept], hw[nbins], hs[nbins], hn[int64, nbins]).
+    """
+    lib = _load()
+    t = _f64(t)
+    x = _f64(x)
+    w = None if w is None else _f64(w)
+    n = t.shape[0]
+    b = np.empty(n, np.int32)
+    hw = np.empty(nbins, np.float64)
+    hs = np.empty(nbins, np.float64)
+    hn = np.empty(nbins, np.int64)
+    m = lib.bls_oracle_bins(_ptr(t), _ptr(x), _ptr(w), n, float(period),
+                            int(nbins), _ptr(b), _ptr(hw), _ptr(hs), _ptr(hn))
+    if m < 0:
+        raise OracleError("oracle rejected the input (status %d)" % m)
+    return b[:m], hw, hs, hn
