@@ -1,0 +1,221 @@
+/*
+ * bls.h -- C ABI of the MI355X (gfx950) box-least-squares periodogram.
+ *
+ * The operation (Law et al. 2011, section 2.2.2, "A Parallel Eclipse Search
+ * Using Graphics Processing Units"): each light curve is phased at every
+ * trial period and a range of box durations and phases is tested with the
+ * box-least-squares statistic the section cites (Kovacs et al. 2002).  For
+ * one curve with times t_i, fluxes x_i and weights w_i (points with w_i = 0
+ * are dropped first):
+ *
+ *   t0 = min t_i,  d_i = t_i - t0,  W = sum w_i,  xbar = sum w_i x_i / W;
+ *   per trial period P: f = 1/P, phase_i = frac(d_i f),
+ *   bin_i = min(trunc(phase_i * nbins), nbins - 1);
+ *   a box is bins j, j+1, ..., j+k-1 (mod nbins) with
+ *   kmin = max(1, lround(qmin nbins)) <= k <= kmax = min(nbins-1, lround(qmax nbins));
+ *   R = sum_{box} w_i,  S = sum_{box} w_i (x_i - xbar),
+ *   v = S^2 / (R (W - R)), valid iff min_in_points <= points in box <= n - 1
+ *   (and S < 0 with BLS_DIP_ONLY);
+ *   SR = sqrt(max v) over valid boxes with v > 0 (0 if none), exact ties to
+ *   the smallest k, then the smallest j;
+ *   depth = -S W / (R (W - R)) of that box (> 0 for a dip),
+ *   phase = j / nbins (box start, relative to t0),
+ *   duration = k P / nbins,
+ *   best_index = first period with the largest SR.
+ *
+ * A period with no valid box reports SR = 0, jstart = kwidth = -1 and NaN
+ * phase, duration and depth.
+ *
+ * Precision: the phase is computed in FP64 with the operation order above,
+ * so bins are those of an FP64 evaluation; per-bin sums are exact
+ * fixed-point integers; box sums and the statistic are FP32.  SR agrees with
+ * an FP64 evaluation to about 1e-6 relative.
+ *
+ * Conventions: every function returns a bls_status.  No function throws.
+ * Caller-owned host arrays are never retained after a synchronous call
+ * returns.  A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef BLS_MI355X_H
+#define BLS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLS_API_VERSION 1
+#define BLS_MAX_NBINS 4096          /* largest nbins a plan accepts */
+
+typedef enum {
+    BLS_OK = 0,
+    BLS_ERR_INVALID_ARG = -1,   /* bad shape, parameter or data            */
+    BLS_ERR_NO_MEMORY = -2,     /* host or device allocation failed        */
+    BLS_ERR_DEVICE = -3,        /* a HIP call failed; see bls_last_error    */
+    BLS_ERR_CAPACITY = -4,      /* shape exceeds the plan's capacities      */
+    BLS_ERR_BUSY = -5,          /* result not ready yet (serving)           */
+    BLS_ERR_TIMEOUT = -6        /* wait timed out (serving)                 */
+} bls_status;
+
+/* Plan flags. */
+enum {
+    BLS_DIP_ONLY = 1u << 0,     /* only boxes below the mean (S < 0) count  */
+    BLS_NO_GRAPH = 1u << 1,     /* never capture/replay HIP graphs          */
+    BLS_NO_AUTOTUNE = 1u << 2   /* use the built-in tile table              */
+};
+
+typedef struct bls_plan bls_plan;
+
+/* Plan configuration.  Initialise with bls_plan_config_init. */
+typedef struct {
+    int32_t device;         /* HIP device ordinal                              */
+    int32_t max_curves;     /* curves per call                                 */
+    int64_t max_points;     /* total points per call (all curves)              */
+    int64_t max_periods;    /* total per-period results per call               */
+    int32_t max_nbins;      /* <= BLS_MAX_NBINS                                */
+    int32_t min_in_points;  /* minimum points inside a valid box (>= 1)        */
+    uint32_t flags;         /* BLS_DIP_ONLY | BLS_NO_GRAPH | BLS_NO_AUTOTUNE   */
+    int32_t reserved;
+    void *hip_stream;       /* hipStream_t to run on; NULL = plan-owned stream */
+} bls_plan_config;
+
+/* Defaults: device 0, 1 curve, 2^20 points, 2^20 periods, max_nbins 4096,
+ * min_in_points 1, no flags, plan-owned stream. */
+void bls_plan_config_init(bls_plan_config *cfg);
+
+/* Create a plan: allocates device buffers sized by cfg on cfg->device.
+ * *out receives the plan (NULL on error).  Errors: INVALID_ARG (bad cfg),
+ * NO_MEMORY, DEVICE. */
+int bls_plan_create(bls_plan **out, const bls_plan_config *cfg);
+
+/* Release a plan and its device memory.  NULL is accepted. */
+int bls_plan_destroy(bls_plan *plan);
+
+/*
+ * One light curve, host arrays (the signature of the method's statement).
+ *   times, flux: [n]; weights: [n] or NULL for unit weights.
+ *   periods: [nperiods] trial periods, finite and > 0.
+ *   nbins: phase bins (2..max_nbins); qmin, qmax: box duty-cycle range,
+ *   0 < qmin <= qmax < 1.
+ * Outputs, [nperiods] each, caller-owned, any may be NULL: sr, phase,
+ * duration, depth (doubles), jstart, kwidth (box start bin and width);
+ * best_index: first period index with the largest SR (may be NULL).
+ * Synchronous.  On any error the outputs are untouched.
+ * Errors: INVALID_ARG (non-finite time or flux of a kept point, negative or
+ * non-finite weight, fewer than 2 kept points, bad period, nbins or q range,
+ * kmin > kmax), CAPACITY (n, nperiods or nbins above the plan's limits),
+ * DEVICE, NO_MEMORY.
+ */
+int bls_search(bls_plan *plan, const double *times, const double *flux,
+               const double *weights, int64_t n, const double *periods,
+               int64_t nperiods, int32_t nbins, double qmin, double qmax,
+               double *sr, double *phase, double *duration, double *depth,
+               int32_t *jstart, int32_t *kwidth, int64_t *best_index);
+
+/*
+ * Many light curves packed end to end (CSR).  Curve c owns points
+ * [n_off[c], n_off[c+1]) of times/flux/weights and periods
+ * [p_off[c], p_off[c+1]) of periods; with p_off == NULL every curve uses
+ * periods[0 .. nperiods_shared).  nbins/qmin/qmax are per-curve arrays, or
+ * NULL to use nbins_all/qmin_all/qmax_all.  Curve c's per-period results
+ * are stored from r_off(c) = p_off ? p_off[c] : c * nperiods_shared.
+ * n_off, p_off, nbins, qmin and qmax are always host arrays; whether times,
+ * flux, weights and periods are host or device pointers depends on the call.
+ */
+typedef struct {
+    int32_t ncurves;
+    int32_t nbins_all;
+    const int64_t *n_off;       /* [ncurves + 1], n_off[0] == 0, non-decreasing */
+    const double *times;
+    const double *flux;
+    const double *weights;      /* NULL = unit weights                       */
+    const int64_t *p_off;       /* [ncurves + 1] or NULL (shared grid)       */
+    const double *periods;
+    int64_t nperiods_shared;
+    const int32_t *nbins;       /* [ncurves] or NULL                         */
+    const double *qmin;         /* [ncurves] or NULL                         */
+    const double *qmax;         /* [ncurves] or NULL                         */
+    double qmin_all;
+    double qmax_all;
+} bls_batch;
+
+/* Host result arrays for bls_search_batch, indexed as described above;
+ * any may be NULL.  best_index has one entry per curve. */
+typedef struct {
+    double *sr;
+    double *phase;
+    double *duration;
+    double *depth;
+    int32_t *jstart;
+    int32_t *kwidth;
+    int64_t *best_index;
+} bls_results;
+
+/* Batch of curves in host memory: one persistent launch for the whole
+ * batch.  Synchronous; outputs untouched on error.  Errors as bls_search. */
+int bls_search_batch(bls_plan *plan, const bls_batch *batch,
+                     const bls_results *out);
+
+/* Device result arrays for bls_search_device (device pointers, all
+ * required): FP32 SR and depth, box start and width, and per-curve best
+ * period index. */
+typedef struct {
+    float *sr;
+    float *depth;
+    int32_t *jstart;
+    int32_t *kwidth;
+    int64_t *best_index;
+} bls_device_results;
+
+/*
+ * Batch whose times, flux, weights and periods are DEVICE pointers on the
+ * plan's device; results go to device arrays.  Shapes and parameters are
+ * checked on the host before anything is queued; the data itself is checked
+ * on the device.  Asynchronous on the plan's stream: the device arrays are
+ * borrowed until bls_synchronize returns.  Curves whose data is invalid get
+ * SR = NaN and are reported by bls_synchronize.  Repeated calls with the
+ * same batch description replay a captured HIP graph.
+ */
+int bls_search_device(bls_plan *plan, const bls_batch *batch,
+                      const bls_device_results *out);
+
+/* Wait for the plan's queued work.  Returns INVALID_ARG if a curve of the
+ * last bls_search_device call had invalid data (message names the first
+ * such curve), DEVICE on a HIP error. */
+int bls_synchronize(bls_plan *plan);
+
+/* The hipStream_t the plan runs on. */
+int bls_get_stream(const bls_plan *plan, void **stream);
+
+/* Widths a (nbins, qmin, qmax) triple selects, per the rule above. */
+int bls_width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin,
+                    int32_t *kmax);
+
+/* Message of the plan's most recent error (empty if none); NUL-terminated,
+ * truncated to len.  plan may be NULL for errors of bls_plan_create. */
+int bls_last_error(const bls_plan *plan, char *buf, size_t len);
+
+/* Static description of a status code. */
+const char *bls_status_string(int status);
+
+/* Timing and shape of the plan's last search call. */
+typedef struct {
+    double search_ms;       /* search kernel, device time (HIP events)      */
+    double total_ms;        /* whole call as queued on the stream           */
+    double trial_points;    /* sum over curves of N_c * nperiods_c          */
+    double box_evals;       /* sum over curves of nbins * nwidths * nperiods */
+    int64_t work_items;     /* (curve, period tile) items                   */
+    int32_t grid;           /* workgroups of the persistent launch          */
+    int32_t block;          /* threads per workgroup                        */
+    int32_t lds_bytes;      /* dynamic LDS per workgroup                    */
+    int32_t graph_replayed; /* 1 if the call replayed a captured graph      */
+} bls_call_stats;
+
+int bls_last_stats(const bls_plan *plan, bls_call_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLS_MI355X_H */

@@ -1,0 +1,334 @@
+"""Python face of the C ABI: same names, argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+class BlsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (status %d): %s" % (bls_status_string(status),
+                                                  status, message))
+        self.status = status
+        self.message = message
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):          # torch tensor (device memory)
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(st: int, plan=None):
+    if st != L.BLS_OK:
+        raise BlsError(st, bls_last_error(plan))
+
+
+# ------------------------------------------------------------------ basics
+def bls_status_string(status: int) -> str:
+    return L.load().bls_status_string(int(status)).decode()
+
+
+def bls_last_error(plan=None) -> str:
+    buf = C.create_string_buffer(1024)
+    L.load().bls_last_error(plan, buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def bls_width_range(nbins: int, qmin: float, qmax: float):
+    """(kmin, kmax) of a duty-cycle range, per the library's rule."""
+    kmin, kmax = C.c_int32(), C.c_int32()
+    _check(L.load().bls_width_range(int(nbins), float(qmin), float(qmax),
+                                    C.byref(kmin), C.byref(kmax)))
+    return kmin.value, kmax.value
+
+
+def bls_plan_config_init(**overrides) -> L.BlsPlanConfig:
+    cfg = L.BlsPlanConfig()
+    L.load().bls_plan_config_init(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def bls_plan_create(cfg: Optional[L.BlsPlanConfig] = None, **overrides):
+    if cfg is None:
+        cfg = bls_plan_config_init(**overrides)
+    plan = C.c_void_p()
+    st = L.load().bls_plan_create(C.byref(plan), C.byref(cfg))
+    if st != L.BLS_OK:
+        raise BlsError(st, bls_last_error(None))
+    return plan
+
+
+def bls_plan_destroy(plan) -> None:
+    if plan:
+        L.load().bls_plan_destroy(plan)
+
+
+def bls_synchronize(plan) -> None:
+    _check(L.load().bls_synchronize(plan), plan)
+
+
+def bls_get_stream(plan) -> int:
+    s = C.c_void_p()
+    _check(L.load().bls_get_stream(plan, C.byref(s)), plan)
+    return s.value or 0
+
+
+def bls_last_stats(plan) -> dict:
+    s = L.BlsCallStats()
+    _check(L.load().bls_last_stats(plan, C.byref(s)), plan)
+    return {f: getattr(s, f) for f, _ in L.BlsCallStats._fields_}
+
+
+# ------------------------------------------------------------------ search
+def bls_search(plan, times, flux, weights, periods, nbins, qmin, qmax):
+    """One light curve in host memory; returns a dict of numpy arrays."""
+    t, x = _f64(times), _f64(flux)
+    w = None if weights is None else _f64(weights)
+    p = _f64(periods)
+    m = p.shape[0]
+    out = dict(sr=np.empty(m), phase=np.empty(m), duration=np.empty(m),
+               depth=np.empty(m), jstart=np.empty(m, np.int32),
+               kwidth=np.empty(m, np.int32))
+    best = C.c_int64(-1)
+    st = L.load().bls_search(
+        plan, _ptr(t), _ptr(x), _ptr(w), t.shape[0], _ptr(p), m, int(nbins),
+        float(qmin), float(qmax), _ptr(out["sr"]), _ptr(out["phase"]),
+        _ptr(out["duration"]), _ptr(out["depth"]), _ptr(out["jstart"]),
+        _ptr(out["kwidth"]), C.byref(best))
+    _check(st, plan)
+    out["best_index"] = best.value
+    return out
+
+
+@dataclass
+class _BatchArgs:
+    struct: L.BlsBatch
+    keep: list
+    nresults: int
+    ncurves: int
+
+
+def _batch(n_off, times, flux, weights, periods, p_off, nbins, qmin, qmax,
+           device: bool) -> _BatchArgs:
+    keep = []
+    b = L.BlsBatch()
+    n_off = np.ascontiguousarray(n_off, dtype=np.int64)
+    keep.append(n_off)
+    nc = n_off.shape[0] - 1
+    b.ncurves = nc
+    b.n_off = n_off.ctypes.data
+    if device:
+        arrs = [times, flux, weights, periods]
+    else:
+        arrs = [_f64(times), _f64(flux),
+                None if weights is None else _f64(weights), _f64(periods)]
+    keep += arrs
+    b.times, b.flux = _ptr(arrs[0]).value, _ptr(arrs[1]).value
+    b.weights = None if arrs[2] is None else _ptr(arrs[2]).value
+    b.periods = _ptr(arrs[3]).value
+    if p_off is None:
+        b.p_off = None
+        b.nperiods_shared = int(arrs[3].shape[0])
+        nres = nc * b.nperiods_shared
+    else:
+        po = np.ascontiguousarray(p_off, dtype=np.int64)
+        keep.append(po)
+        b.p_off = po.ctypes.data
+        b.nperiods_shared = 0
+        nres = int(po[-1])
+    if np.ndim(nbins) == 0:
+        b.nbins_all, b.nbins = int(nbins), None
+    else:
+        nb = np.ascontiguousarray(nbins, dtype=np.int32)
+        keep.append(nb)
+        b.nbins = nb.ctypes.data
+    for name in ("qmin", "qmax"):
+        v = qmin if name == "qmin" else qmax
+        if np.ndim(v) == 0:
+            setattr(b, name + "_all", float(v))
+            setattr(b, name, None)
+        else:
+            a = _f64(v)
+            keep.append(a)
+            setattr(b, name, a.ctypes.data)
+    return _BatchArgs(b, keep, nres, nc)
+
+
+def bls_search_batch(plan, n_off, times, flux, weights, periods, p_off,
+                     nbins, qmin, qmax):
+    """Many curves in host memory (CSR); returns a dict of numpy arrays."""
+    ba = _batch(n_off, times, flux, weights, periods, p_off, nbins, qmin,
+                qmax, device=False)
+    m = ba.nresults
+    out = dict(sr=np.empty(m), phase=np.empty(m), duration=np.empty(m),
+               depth=np.empty(m), jstart=np.empty(m, np.int32),
+               kwidth=np.empty(m, np.int32),
+               best_index=np.empty(ba.ncurves, np.int64))
+    r = L.BlsResults(*[out[k].ctypes.data for k in
+                       ("sr", "phase", "duration", "depth", "jstart",
+                        "kwidth", "best_index")])
+    _check(L.load().bls_search_batch(plan, C.byref(ba.struct), C.byref(r)),
+           plan)
+    return out
+
+
+def bls_search_device(plan, n_off, times, flux, weights, periods, p_off,
+                      nbins, qmin, qmax, sr, depth, jstart, kwidth,
+                      best_index):
+    """Device tensors in, device tensors out; asynchronous on the plan stream.
+
+    times/flux/weights/periods/sr/depth/jstart/kwidth/best_index are torch
+    tensors on the plan's device (float64 inputs; float32 sr/depth, int32
+    jstart/kwidth, int64 best_index).  Call bls_synchronize before reading.
+    """
+    ba = _batch(n_off, times, flux, weights, periods, p_off, nbins, qmin,
+                qmax, device=True)
+    o = L.BlsDeviceResults(sr.data_ptr(), depth.data_ptr(), jstart.data_ptr(),
+                           kwidth.data_ptr(), best_index.data_ptr())
+    _check(L.load().bls_search_device(plan, C.byref(ba.struct), C.byref(o)),
+           plan)
+
+
+class Plan:
+    """Owning wrapper of a bls_plan (closes on exit)."""
+
+    def __init__(self, **cfg):
+        self.handle = bls_plan_create(**cfg)
+
+    def close(self):
+        if self.handle:
+            bls_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+def bls_server_config_init(**overrides) -> L.BlsServerConfig:
+    cfg = L.BlsServerConfig()
+    L.load().bls_server_config_init(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def _server_error(srv) -> str:
+    buf = C.create_string_buffer(1024)
+    L.load().bls_server_last_error(srv, buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def bls_server_create(cfg: Optional[L.BlsServerConfig] = None, **overrides):
+    if cfg is None:
+        cfg = bls_server_config_init(**overrides)
+    srv = C.c_void_p()
+    st = L.load().bls_server_create(C.byref(srv), C.byref(cfg))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(None))
+    return srv
+
+
+def bls_server_submit(srv, times, flux, weights, periods, nbins, qmin,
+                      qmax) -> int:
+    """Queue one request (inputs are copied); returns its ticket."""
+    t, x = _f64(times), _f64(flux)
+    w = None if weights is None else _f64(weights)
+    p = _f64(periods)
+    req = L.BlsRequest(t.ctypes.data, x.ctypes.data,
+                       None if w is None else w.ctypes.data, t.shape[0],
+                       p.ctypes.data, p.shape[0], int(nbins), 0, float(qmin),
+                       float(qmax))
+    ticket = C.c_uint64()
+    st = L.load().bls_server_submit(srv, C.byref(req), C.byref(ticket))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+    return ticket.value
+
+
+def _result_dict(r: L.BlsResult) -> dict:
+    m = int(r.nperiods)
+    out = dict(status=int(r.status), best_index=int(r.best_index),
+               submit_s=r.submit_s, admit_s=r.admit_s, done_s=r.done_s)
+    if r.status == L.BLS_OK and m > 0:
+        out["sr"] = np.ctypeslib.as_array(
+            C.cast(r.sr, C.POINTER(C.c_float)), (m,)).copy()
+        out["depth"] = np.ctypeslib.as_array(
+            C.cast(r.depth, C.POINTER(C.c_float)), (m,)).copy()
+        out["jstart"] = np.ctypeslib.as_array(
+            C.cast(r.jstart, C.POINTER(C.c_int32)), (m,)).copy()
+        out["kwidth"] = np.ctypeslib.as_array(
+            C.cast(r.kwidth, C.POINTER(C.c_int32)), (m,)).copy()
+    return out
+
+
+def bls_server_poll(srv, ticket: int):
+    """Result dict, or None while the request is still in flight."""
+    r = L.BlsResult()
+    st = L.load().bls_server_poll(srv, C.c_uint64(ticket), C.byref(r))
+    if st == L.BLS_ERR_BUSY:
+        return None
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+    return _result_dict(r)
+
+
+def bls_server_wait(srv, ticket: int, timeout_s: float = 60.0) -> dict:
+    r = L.BlsResult()
+    st = L.load().bls_server_wait(srv, C.c_uint64(ticket), C.byref(r),
+                                  float(timeout_s))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+    return _result_dict(r)
+
+
+def bls_server_release(srv, ticket: int) -> None:
+    st = L.load().bls_server_release(srv, C.c_uint64(ticket))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+
+
+def bls_server_stats(srv) -> dict:
+    s = L.BlsServerStats()
+    st = L.load().bls_server_stats(srv, C.byref(s))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+    return {f: getattr(s, f) for f, _ in L.BlsServerStats._fields_}
+
+
+def bls_server_reset_stats(srv) -> None:
+    L.load().bls_server_reset_stats(srv)
+
+
+def bls_server_drain(srv, timeout_s: float = 60.0) -> None:
+    st = L.load().bls_server_drain(srv, float(timeout_s))
+    if st != L.BLS_OK:
+        raise BlsError(st, _server_error(srv))
+
+
+def bls_server_destroy(srv) -> None:
+    if srv:
+        L.load().bls_server_destroy(srv)

@@ -1,0 +1,98 @@
+// Internal layout shared by the host runtime and the gfx950 kernels.
+//
+// Data layout in HBM (one call, all curves packed end to end):
+//   prep_dt[i]  f64  t_i - t0 of point i (0 for dropped points)
+//   prep_q[i]   i32  round(y_i 2^es) (unit weights) or round(w_i y_i 2^es)
+//   prep_qw[i]  i32  round(w_i 2^ew), -1 for a dropped (zero-weight) point
+//                    (weighted curves only)
+//   curves[c]   CurveDesc, host fields first, prep fields written on device
+//   seg_*       work segments: items [seg_start[s], seg_start[s+1]) are the
+//               period tiles seg_tile0[s] + ... of curve seg_curve[s]
+#pragma once
+#include <stdint.h>
+
+namespace bls {
+
+constexpr int kBlock = 256;        // threads per workgroup
+constexpr int kTileMax = 32;       // largest period tile
+constexpr int kPPT = 8;            // points held in registers per thread
+constexpr int kQBitsMax = 30;      // fixed-point magnitude bits per point
+
+enum CurveStatus : int32_t {
+  kCurveOk = 0,
+  kCurveBadData = 1,    // non-finite kept time/flux, bad weight
+  kCurveTooFew = 2,     // fewer than two kept points or zero total weight
+};
+
+struct CurveDesc {
+  // ---- written by the host planner
+  int64_t n_off;        // first point in the packed arrays
+  int64_t n;            // input points (including zero-weight ones)
+  int64_t p_off;        // first trial period
+  int64_t r_off;        // first result slot
+  int32_t nperiods;
+  int32_t nbins;
+  int32_t kmin;
+  int32_t kmax;
+  int32_t tile;         // periods per work item
+  int32_t shift;        // count field starts at this bit of a bin word
+  int32_t qbits;        // magnitude bits of a point's fixed-point value
+  int32_t weighted;     // 1 if a weight array is present
+  // ---- written by the prep kernel
+  double t0;            // min time over kept points
+  double W;             // sum of weights (FP64)
+  double xbar;          // weighted mean flux (FP64)
+  double out_scale;     // SR and depth of scan units -> flux units
+  float Wf;             // total weight in scan units
+  int32_t n_eff;        // kept points
+  int32_t status;       // CurveStatus
+  int32_t es;           // exponent of the S fixed-point scale
+  int32_t ew;           // exponent of the weight fixed-point scale
+  int32_t pad;
+};
+
+struct PrepArgs {
+  CurveDesc *curves;
+  int32_t ncurves;
+  const double *t;
+  const double *x;
+  const double *w;      // nullptr: unit weights
+  double *dt;
+  int32_t *q;
+  int32_t *qw;
+};
+
+struct SearchArgs {
+  const CurveDesc *curves;
+  const double *periods;
+  const double *dt;
+  const int32_t *q;
+  const int32_t *qw;
+  const int64_t *seg_start;   // [nseg + 1]
+  const int32_t *seg_curve;   // [nseg]
+  const int32_t *seg_tile0;   // [nseg]
+  int32_t nseg;
+  int32_t min_in_points;
+  int64_t nitems;
+  unsigned long long *counter;  // work counter, zeroed before the launch
+  float *sr;
+  float *depth;
+  int32_t *jstart;
+  int32_t *kwidth;
+  unsigned long long *best_key;  // per curve, zeroed before the launch
+  int32_t hist_bytes;         // dynamic LDS for histograms
+};
+
+// Launch wrappers (bls_kernels.hip).  All return hipError_t as int.
+int launch_fill(unsigned long long *counter, unsigned long long *keys,
+                int32_t nkeys,
+                void *stream);
+int launch_prep(const PrepArgs &a, void *stream);
+int launch_search(const SearchArgs &a, bool weighted, bool dip_only, int grid,
+                  void *stream);
+int launch_best_index(unsigned long long *keys, int32_t n, void *stream);
+// Workgroups of the search kernel one CU holds at this LDS size.
+int search_blocks_per_cu(bool weighted, bool dip_only, int hist_bytes,
+                         int *blocks);
+
+}  // namespace bls

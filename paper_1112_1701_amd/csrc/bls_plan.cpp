@@ -1,0 +1,809 @@
+// Host runtime of the BLS library: plan creation, validation, planning of
+// (curve, period tile) work items, launch sequencing, HIP graph replay and
+// the C ABI of include/bls.h.
+//
+// The operation and its conventions are those stated in include/bls.h (Law
+// et al. 2011, section 2.2.2, and the box-least-squares statistic it cites).
+#include "bls_plan.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <new>
+#include <numeric>
+
+namespace bls {
+namespace {
+
+thread_local std::string g_create_error;
+std::atomic<long long> g_alloc_count{0};
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t bytes) {
+  const unsigned char *p = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < bytes; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+template <class T>
+uint64_t mix(uint64_t h, const T &v) {
+  return fnv1a(h, &v, sizeof(T));
+}
+
+int cbits_of(int64_t n) {
+  int b = 0;
+  while (b < 63 && (int64_t(1) << b) <= n) ++b;
+  return b;  // bit length of n
+}
+
+void free_dev(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+hipError_t device_alloc(void **ptr, size_t bytes) {
+  *ptr = nullptr;
+  const long long k = ++g_alloc_count;
+  const char *hook = getenv("BLS_DEBUG_FAIL_ALLOC");
+  if (hook && *hook) {
+    // "N": the N-th device allocation of the process fails; "all": every one.
+    if (strcmp(hook, "all") == 0 || atoll(hook) == k) return hipErrorOutOfMemory;
+  }
+  return hipMalloc(ptr, bytes > 0 ? bytes : 1);
+}
+
+int set_error(bls_plan *p, int status, const std::string &msg) {
+  if (p)
+    p->last_error = msg;
+  else
+    g_create_error = msg;
+  return status;
+}
+
+int hip_error(bls_plan *p, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_error(p, e == hipErrorOutOfMemory ? BLS_ERR_NO_MEMORY : BLS_ERR_DEVICE, m);
+}
+
+int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t *kmax) {
+  if (nbins < 2 || !(qmin > 0.0) || !(qmax < 1.0) || !(qmin <= qmax)) return BLS_ERR_INVALID_ARG;
+  long lo = lround(qmin * (double)nbins);
+  long hi = lround(qmax * (double)nbins);
+  if (lo < 1) lo = 1;
+  if (hi > nbins - 1) hi = nbins - 1;
+  if (kmin) *kmin = (int32_t)lo;
+  if (kmax) *kmax = (int32_t)hi;
+  return lo <= hi ? BLS_OK : BLS_ERR_INVALID_ARG;
+}
+
+int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
+                   std::vector<CurveShape> &shapes, std::string &err) {
+  char msg[256];
+  if (b.ncurves < 1 || b.n_off == nullptr || b.times == nullptr || b.flux == nullptr ||
+      b.periods == nullptr) {
+    err = "batch needs ncurves >= 1 and non-NULL n_off, times, flux, periods";
+    return BLS_ERR_INVALID_ARG;
+  }
+  if (b.ncurves > cfg.max_curves) {
+    snprintf(msg, sizeof msg, "%d curves exceed the plan's max_curves %d", b.ncurves,
+             cfg.max_curves);
+    err = msg;
+    return BLS_ERR_CAPACITY;
+  }
+  if (b.n_off[0] != 0) {
+    err = "n_off[0] must be 0";
+    return BLS_ERR_INVALID_ARG;
+  }
+  if (b.p_off == nullptr && b.nperiods_shared < 1) {
+    err = "shared period grid needs nperiods_shared >= 1";
+    return BLS_ERR_INVALID_ARG;
+  }
+  if (b.p_off != nullptr && b.p_off[0] != 0) {
+    err = "p_off[0] must be 0";
+    return BLS_ERR_INVALID_ARG;
+  }
+  shapes.resize(b.ncurves);
+  int64_t total_results = 0;
+  for (int c = 0; c < b.ncurves; ++c) {
+    CurveShape &s = shapes[c];
+    s.n_off = b.n_off[c];
+    s.n = b.n_off[c + 1] - b.n_off[c];
+    if (s.n < 2) {
+      snprintf(msg, sizeof msg, "curve %d has %lld points (need >= 2)", c, (long long)s.n);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+    if (s.n > (int64_t(1) << 24)) {
+      snprintf(msg, sizeof msg, "curve %d has %lld points (at most 2^24)", c, (long long)s.n);
+      err = msg;
+      return BLS_ERR_CAPACITY;
+    }
+    int64_t np;
+    if (b.p_off) {
+      s.p_off = b.p_off[c];
+      np = b.p_off[c + 1] - b.p_off[c];
+      s.r_off = s.p_off;
+    } else {
+      s.p_off = 0;
+      np = b.nperiods_shared;
+      s.r_off = (int64_t)c * b.nperiods_shared;
+    }
+    if (np < 1 || np > INT32_MAX) {
+      snprintf(msg, sizeof msg, "curve %d has %lld trial periods", c, (long long)np);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+    s.nperiods = (int32_t)np;
+    total_results += np;
+    s.nbins = b.nbins ? b.nbins[c] : b.nbins_all;
+    const double qmin = b.qmin ? b.qmin[c] : b.qmin_all;
+    const double qmax = b.qmax ? b.qmax[c] : b.qmax_all;
+    if (s.nbins < 2) {
+      snprintf(msg, sizeof msg, "curve %d: nbins %d < 2", c, s.nbins);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+    if (s.nbins > cfg.max_nbins) {
+      snprintf(msg, sizeof msg, "curve %d: nbins %d exceeds max_nbins %d", c, s.nbins,
+               cfg.max_nbins);
+      err = msg;
+      return BLS_ERR_CAPACITY;
+    }
+    if (width_range(s.nbins, qmin, qmax, &s.kmin, &s.kmax) != BLS_OK) {
+      snprintf(msg, sizeof msg, "curve %d: bad duty-cycle range [%g, %g] for %d bins", c, qmin,
+               qmax, s.nbins);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+  }
+  const int64_t total_points = b.n_off[b.ncurves];
+  if (total_points > cfg.max_points) {
+    snprintf(msg, sizeof msg, "%lld points exceed the plan's max_points %lld",
+             (long long)total_points, (long long)cfg.max_points);
+    err = msg;
+    return BLS_ERR_CAPACITY;
+  }
+  if (total_results > cfg.max_periods) {
+    snprintf(msg, sizeof msg, "%lld results exceed the plan's max_periods %lld",
+             (long long)total_results, (long long)cfg.max_periods);
+    err = msg;
+    return BLS_ERR_CAPACITY;
+  }
+  if (!check_data) return BLS_OK;
+
+  // Host data: periods, then points (zero-weight points are dropped first).
+  const int64_t nper_total = b.p_off ? b.p_off[b.ncurves] : b.nperiods_shared;
+  for (int64_t i = 0; i < nper_total; ++i) {
+    const double P = b.periods[i];
+    if (!isfinite(P) || !(P > 0.0)) {
+      snprintf(msg, sizeof msg, "trial period %lld is %g (must be finite and > 0)",
+               (long long)i, P);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+  }
+  for (int c = 0; c < b.ncurves; ++c) {
+    const CurveShape &s = shapes[c];
+    int64_t kept = 0;
+    double W = 0.0;
+    for (int64_t i = s.n_off; i < s.n_off + s.n; ++i) {
+      const double w = b.weights ? b.weights[i] : 1.0;
+      if (!(w >= 0.0) || isinf(w)) {
+        snprintf(msg, sizeof msg, "curve %d point %lld: weight %g (must be finite, >= 0)", c,
+                 (long long)(i - s.n_off), w);
+        err = msg;
+        return BLS_ERR_INVALID_ARG;
+      }
+      if (w == 0.0) continue;
+      if (!isfinite(b.times[i]) || !isfinite(b.flux[i])) {
+        snprintf(msg, sizeof msg, "curve %d point %lld: non-finite time or flux", c,
+                 (long long)(i - s.n_off));
+        err = msg;
+        return BLS_ERR_INVALID_ARG;
+      }
+      ++kept;
+      W += w;
+    }
+    if (kept < 2 || !(W > 0.0) || !isfinite(W)) {
+      snprintf(msg, sizeof msg, "curve %d: %lld points with positive weight (need >= 2)", c,
+               (long long)kept);
+      err = msg;
+      return BLS_ERR_INVALID_ARG;
+    }
+  }
+  return BLS_OK;
+}
+
+int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
+               const TileChoice &tc, PlannedBatch &out) {
+  const int nc = (int)shapes.size();
+  const int wpb = weighted ? 2 : 1;
+  out = PlannedBatch{};
+  out.ncurves = nc;
+  out.weighted = weighted;
+
+  // Per-curve tile: as many periods as fit the LDS budget, at least one.
+  int hist_bytes = 0;
+  std::vector<double> item_cost(nc);
+  for (int c = 0; c < nc; ++c) {
+    const CurveShape &s = shapes[c];
+    CurveDesc &d = p->h_curves[c];
+    memset(&d, 0, sizeof d);
+    d.n_off = s.n_off;
+    d.n = s.n;
+    d.p_off = s.p_off;
+    d.r_off = s.r_off;
+    d.nperiods = s.nperiods;
+    d.nbins = s.nbins;
+    d.kmin = s.kmin;
+    d.kmax = s.kmax;
+    const int cb = cbits_of(s.n);
+    d.shift = 64 - cb;
+    d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
+    d.weighted = weighted ? 1 : 0;
+    const int per_period = (s.nbins + s.kmax - 1) * 8 * wpb;
+    int T = std::max(1, tc.lds_budget / per_period);
+    T = std::min(T, std::min(tc.tile_cap, kTileMax));
+    T = std::min(T, s.nperiods);
+    d.tile = T;
+    hist_bytes = std::max(hist_bytes, T * per_period);
+    const double nw = (double)(s.kmax - s.kmin + 1);
+    item_cost[c] = (double)T * ((double)s.n + 1.6 * (double)s.nbins * nw);
+    out.total_points += s.n;
+    out.total_results += s.nperiods;
+    out.trial_points += (double)s.n * (double)s.nperiods;
+    out.box_evals += (double)s.nbins * nw * (double)s.nperiods;
+  }
+  if (hist_bytes > p->max_lds - 1024) {
+    return set_error(p, BLS_ERR_CAPACITY,
+                     "one period's histogram needs " + std::to_string(hist_bytes) +
+                         " bytes of LDS, more than a workgroup has");
+  }
+
+  // Largest items first, so the persistent grid drains evenly.
+  p->order.resize(nc);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  std::stable_sort(p->order.begin(), p->order.end(),
+                   [&](int a, int b) { return item_cost[a] > item_cost[b]; });
+  int64_t items = 0;
+  for (int s = 0; s < nc; ++s) {
+    const int c = p->order[s];
+    const CurveDesc &d = p->h_curves[c];
+    p->h_seg_start[s] = items;
+    p->h_seg_curve[s] = c;
+    p->h_seg_tile0[s] = 0;
+    items += (d.nperiods + d.tile - 1) / d.tile;
+  }
+  p->h_seg_start[nc] = items;
+  out.nseg = nc;
+  out.nitems = items;
+  out.hist_bytes = hist_bytes;
+
+  int per_cu = 0;
+  hipError_t e = (hipError_t)search_blocks_per_cu(weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0,
+                                                  hist_bytes, &per_cu);
+  if (e != hipSuccess) return hip_error(p, e, "occupancy query");
+  if (per_cu < 1) return set_error(p, BLS_ERR_CAPACITY, "search kernel does not fit a CU");
+  if (tc.occupancy > 0) per_cu = std::min(per_cu, tc.occupancy);
+  const int64_t grid = std::min<int64_t>(items, (int64_t)p->num_cus * per_cu);
+  out.grid = (int32_t)std::max<int64_t>(grid, 1);
+  return BLS_OK;
+}
+
+int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
+                   const double *w, const double *periods, float *sr, float *depth, int32_t *js,
+                   int32_t *ks, int64_t *best, bool timed) {
+  hipStream_t st = p->stream;
+  hipError_t e;
+  const int nc = pb.ncurves;
+  e = hipMemcpyAsync(p->d_curves, p->h_curves, sizeof(CurveDesc) * nc, hipMemcpyHostToDevice,
+                     st);
+  if (e != hipSuccess) return hip_error(p, e, "upload curve descriptors");
+  e = hipMemcpyAsync(p->d_seg_start, p->h_seg_start, sizeof(int64_t) * (pb.nseg + 1),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_error(p, e, "upload segments");
+  e = hipMemcpyAsync(p->d_seg_curve, p->h_seg_curve, sizeof(int32_t) * pb.nseg,
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_error(p, e, "upload segments");
+  e = hipMemcpyAsync(p->d_seg_tile0, p->h_seg_tile0, sizeof(int32_t) * pb.nseg,
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_error(p, e, "upload segments");
+
+  unsigned long long *keys = reinterpret_cast<unsigned long long *>(best);
+  e = (hipError_t)launch_fill(p->d_counter, keys, nc, st);
+  if (e != hipSuccess) return hip_error(p, e, "launch fill");
+
+  PrepArgs pa;
+  pa.curves = p->d_curves;
+  pa.ncurves = nc;
+  pa.t = t;
+  pa.x = x;
+  pa.w = w;
+  pa.dt = p->d_dt;
+  pa.q = p->d_q;
+  pa.qw = p->d_qw;
+  e = (hipError_t)launch_prep(pa, st);
+  if (e != hipSuccess) return hip_error(p, e, "launch prep");
+
+  SearchArgs sa;
+  sa.curves = p->d_curves;
+  sa.periods = periods;
+  sa.dt = p->d_dt;
+  sa.q = p->d_q;
+  sa.qw = pb.weighted ? p->d_qw : nullptr;
+  sa.seg_start = p->d_seg_start;
+  sa.seg_curve = p->d_seg_curve;
+  sa.seg_tile0 = p->d_seg_tile0;
+  sa.nseg = pb.nseg;
+  sa.min_in_points = p->cfg.min_in_points;
+  sa.nitems = pb.nitems;
+  sa.counter = p->d_counter;
+  sa.sr = sr;
+  sa.depth = depth;
+  sa.jstart = js;
+  sa.kwidth = ks;
+  sa.best_key = keys;
+  sa.hist_bytes = pb.hist_bytes;
+  if (timed) {
+    e = hipEventRecord(p->ev_search0, st);
+    if (e != hipSuccess) return hip_error(p, e, "event record");
+  }
+  e = (hipError_t)launch_search(sa, pb.weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0, pb.grid,
+                                st);
+  if (e != hipSuccess) return hip_error(p, e, "launch search");
+  if (timed) {
+    e = hipEventRecord(p->ev_search1, st);
+    if (e != hipSuccess) return hip_error(p, e, "event record");
+  }
+  e = (hipError_t)launch_best_index(keys, nc, st);
+  if (e != hipSuccess) return hip_error(p, e, "launch best index");
+  return BLS_OK;
+}
+
+TileChoice default_tiles(bool weighted) {
+  TileChoice tc;
+  tc.lds_budget = weighted ? 40960 : 32768;
+  tc.tile_cap = kTileMax;
+  tc.occupancy = 0;
+  return tc;
+}
+
+}  // namespace bls
+
+using namespace bls;
+
+namespace {
+
+void fill_stats(bls_plan *p, const PlannedBatch &pb, bool replayed) {
+  p->stats.trial_points = pb.trial_points;
+  p->stats.box_evals = pb.box_evals;
+  p->stats.work_items = pb.nitems;
+  p->stats.grid = pb.grid;
+  p->stats.block = kBlock;
+  p->stats.lds_bytes = pb.hist_bytes;
+  p->stats.graph_replayed = replayed ? 1 : 0;
+}
+
+int ensure_staging(bls_plan *p) {
+  if (p->staging) return BLS_OK;
+  const size_t np = (size_t)p->cfg.max_points, nr = (size_t)p->cfg.max_periods,
+               nc = (size_t)p->cfg.max_curves;
+  struct {
+    void **ptr;
+    size_t bytes;
+  } req[] = {{(void **)&p->d_t, np * 8},      {(void **)&p->d_x, np * 8},
+             {(void **)&p->d_w, np * 8},      {(void **)&p->d_periods, nr * 8},
+             {(void **)&p->d_sr, nr * 4},     {(void **)&p->d_depth, nr * 4},
+             {(void **)&p->d_j, nr * 4},      {(void **)&p->d_k, nr * 4},
+             {(void **)&p->d_best, nc * 8}};
+  for (auto &r : req) {
+    hipError_t e = device_alloc(r.ptr, r.bytes);
+    if (e != hipSuccess) {
+      for (auto &q : req) {
+        free_dev(*q.ptr);
+        *q.ptr = nullptr;
+      }
+      return hip_error(p, e, "allocate host-path staging");
+    }
+  }
+  p->staging = true;
+  return BLS_OK;
+}
+
+int check_device_status(bls_plan *p, int ncurves) {
+  std::vector<CurveDesc> cds(ncurves);
+  hipError_t e = hipMemcpy(cds.data(), p->d_curves, sizeof(CurveDesc) * ncurves,
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(p, e, "read curve status");
+  for (int c = 0; c < ncurves; ++c) {
+    if (cds[c].status != kCurveOk) {
+      char msg[160];
+      snprintf(msg, sizeof msg, "curve %d: %s", c,
+               cds[c].status == kCurveBadData
+                   ? "non-finite time/flux of a kept point, or a negative/non-finite weight"
+                   : "fewer than two points with positive weight");
+      return set_error(p, BLS_ERR_INVALID_ARG, msg);
+    }
+  }
+  return BLS_OK;
+}
+
+// Host-array search of a validated batch (shared by bls_search and
+// bls_search_batch).
+int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &shapes,
+                const bls_results &out) {
+  int st = ensure_staging(p);
+  if (st != BLS_OK) return st;
+  const bool weighted = b.weights != nullptr;
+  TileChoice tc = choose_tiles(p, shapes, weighted);
+  PlannedBatch pb;
+  st = plan_batch(p, shapes, weighted, tc, pb);
+  if (st != BLS_OK) return st;
+  p->graph_valid = false;  // descriptors were rewritten
+
+  const int64_t npts = b.n_off[b.ncurves];
+  const int64_t nper = b.p_off ? b.p_off[b.ncurves] : b.nperiods_shared;
+  hipStream_t s = p->stream;
+  hipError_t e;
+  if ((e = hipEventRecord(p->ev_begin, s)) != hipSuccess) return hip_error(p, e, "event");
+  if ((e = hipMemcpyAsync(p->d_t, b.times, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(p, e, "upload times");
+  if ((e = hipMemcpyAsync(p->d_x, b.flux, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(p, e, "upload flux");
+  if (weighted &&
+      (e = hipMemcpyAsync(p->d_w, b.weights, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(p, e, "upload weights");
+  if ((e = hipMemcpyAsync(p->d_periods, b.periods, nper * 8, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_error(p, e, "upload periods");
+  st = enqueue_search(p, pb, p->d_t, p->d_x, weighted ? p->d_w : nullptr, p->d_periods, p->d_sr,
+                      p->d_depth, p->d_j, p->d_k, p->d_best, true);
+  if (st != BLS_OK) return st;
+  if ((e = hipEventRecord(p->ev_end, s)) != hipSuccess) return hip_error(p, e, "event");
+
+  const int64_t nres = pb.total_results;
+  std::vector<float> sr(nres), depth(nres);
+  std::vector<int32_t> js(nres), ks(nres);
+  std::vector<int64_t> best(b.ncurves);
+  if ((e = hipMemcpyAsync(sr.data(), p->d_sr, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(depth.data(), p->d_depth, nres * 4, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(js.data(), p->d_j, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(ks.data(), p->d_k, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(best.data(), p->d_best, b.ncurves * 8, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+    return hip_error(p, e, "download results");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(p, e, "search");
+  st = check_device_status(p, b.ncurves);
+  if (st != BLS_OK) return st;
+
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1);
+  p->stats.search_ms = ms;
+  (void)hipEventElapsedTime(&ms, p->ev_begin, p->ev_end);
+  p->stats.total_ms = ms;
+  fill_stats(p, pb, false);
+
+  // Results: (value, box) per period at r_off; phase and duration from j, k.
+  for (int c = 0; c < b.ncurves; ++c) {
+    const CurveShape &cs = shapes[c];
+    const double *per = b.periods + cs.p_off;
+    for (int32_t i = 0; i < cs.nperiods; ++i) {
+      const int64_t r = cs.r_off + i;
+      const bool none = ks[r] < 0;
+      if (out.sr) out.sr[r] = (double)sr[r];
+      if (out.depth) out.depth[r] = none ? NAN : (double)depth[r];
+      if (out.jstart) out.jstart[r] = js[r];
+      if (out.kwidth) out.kwidth[r] = ks[r];
+      if (out.phase) out.phase[r] = none ? NAN : (double)js[r] / (double)cs.nbins;
+      if (out.duration) out.duration[r] = none ? NAN : (double)ks[r] * per[i] / (double)cs.nbins;
+    }
+    if (out.best_index) out.best_index[c] = best[c];
+  }
+  p->last = pb;
+  return BLS_OK;
+}
+
+uint64_t batch_signature(const bls_plan *p, const bls_batch &b, const bls_device_results &o) {
+  uint64_t h = 1469598103934665603ull;
+  h = mix(h, b.ncurves);
+  h = mix(h, b.times);
+  h = mix(h, b.flux);
+  h = mix(h, b.weights);
+  h = mix(h, b.periods);
+  h = mix(h, b.nperiods_shared);
+  h = mix(h, b.nbins_all);
+  h = mix(h, b.qmin_all);
+  h = mix(h, b.qmax_all);
+  h = fnv1a(h, b.n_off, sizeof(int64_t) * (b.ncurves + 1));
+  if (b.p_off) h = fnv1a(h, b.p_off, sizeof(int64_t) * (b.ncurves + 1));
+  if (b.nbins) h = fnv1a(h, b.nbins, sizeof(int32_t) * b.ncurves);
+  if (b.qmin) h = fnv1a(h, b.qmin, sizeof(double) * b.ncurves);
+  if (b.qmax) h = fnv1a(h, b.qmax, sizeof(double) * b.ncurves);
+  h = mix(h, o.sr);
+  h = mix(h, o.depth);
+  h = mix(h, o.jstart);
+  h = mix(h, o.kwidth);
+  h = mix(h, o.best_index);
+  h = mix(h, p->cfg.flags);
+  h = mix(h, p->cfg.min_in_points);
+  return h;
+}
+
+void drop_graph(bls_plan *p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->graph_valid = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bls_plan_config_init(bls_plan_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->device = 0;
+  cfg->max_curves = 1;
+  cfg->max_points = int64_t(1) << 20;
+  cfg->max_periods = int64_t(1) << 20;
+  cfg->max_nbins = BLS_MAX_NBINS;
+  cfg->min_in_points = 1;
+  cfg->flags = 0;
+  cfg->hip_stream = nullptr;
+}
+
+int bls_plan_create(bls_plan **out, const bls_plan_config *cfg_in) {
+  if (!out) return set_error(nullptr, BLS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  bls_plan_config cfg;
+  if (cfg_in)
+    cfg = *cfg_in;
+  else
+    bls_plan_config_init(&cfg);
+  if (cfg.min_in_points <= 0) cfg.min_in_points = 1;
+  if (cfg.max_curves < 1 || cfg.max_points < 2 || cfg.max_periods < 1 || cfg.max_nbins < 2 ||
+      cfg.max_nbins > BLS_MAX_NBINS || cfg.max_curves > (1 << 30))
+    return set_error(nullptr, BLS_ERR_INVALID_ARG, "bad plan capacities");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0)
+    return set_error(nullptr, BLS_ERR_DEVICE, "no HIP device available");
+  if (cfg.device < 0 || cfg.device >= ndev)
+    return set_error(nullptr, BLS_ERR_INVALID_ARG, "device ordinal out of range");
+
+  bls_plan *p = new (std::nothrow) bls_plan();
+  if (!p) return set_error(nullptr, BLS_ERR_NO_MEMORY, "host allocation");
+  p->cfg = cfg;
+  p->device = cfg.device;
+  auto fail = [&](int st) {
+    g_create_error = p->last_error;
+    bls_plan_destroy(p);
+    return st;
+  };
+  if ((e = hipSetDevice(p->device)) != hipSuccess) return fail(hip_error(p, e, "set device"));
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, p->device)) != hipSuccess)
+    return fail(hip_error(p, e, "device properties"));
+  p->num_cus = prop.multiProcessorCount;
+  p->max_lds = (int)prop.sharedMemPerBlock;
+  if (cfg.hip_stream) {
+    p->stream = (hipStream_t)cfg.hip_stream;
+  } else {
+    if ((e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking)) != hipSuccess)
+      return fail(hip_error(p, e, "create stream"));
+    p->own_stream = true;
+  }
+  for (hipEvent_t *ev : {&p->ev_begin, &p->ev_search0, &p->ev_search1, &p->ev_end})
+    if ((e = hipEventCreate(ev)) != hipSuccess) return fail(hip_error(p, e, "create event"));
+
+  const size_t nc = (size_t)cfg.max_curves, npt = (size_t)cfg.max_points;
+  struct {
+    void **ptr;
+    size_t bytes;
+  } req[] = {{(void **)&p->d_curves, sizeof(CurveDesc) * nc},
+             {(void **)&p->d_seg_start, sizeof(int64_t) * (nc + 1)},
+             {(void **)&p->d_seg_curve, sizeof(int32_t) * nc},
+             {(void **)&p->d_seg_tile0, sizeof(int32_t) * nc},
+             {(void **)&p->d_dt, 8 * npt},
+             {(void **)&p->d_q, 4 * npt},
+             {(void **)&p->d_qw, 4 * npt},
+             {(void **)&p->d_counter, 64}};
+  for (auto &r : req)
+    if ((e = device_alloc(r.ptr, r.bytes)) != hipSuccess)
+      return fail(hip_error(p, e, "allocate plan buffers"));
+  if ((e = hipHostMalloc((void **)&p->h_curves, sizeof(CurveDesc) * nc, 0)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&p->h_seg_start, sizeof(int64_t) * (nc + 1), 0)) !=
+          hipSuccess ||
+      (e = hipHostMalloc((void **)&p->h_seg_curve, sizeof(int32_t) * nc, 0)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&p->h_seg_tile0, sizeof(int32_t) * nc, 0)) != hipSuccess)
+    return fail(hip_error(p, e, "allocate pinned descriptors"));
+  *out = p;
+  return BLS_OK;
+}
+
+int bls_plan_destroy(bls_plan *p) {
+  if (!p) return BLS_OK;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  drop_graph(p);
+  for (void *d : {(void *)p->d_curves, (void *)p->d_seg_start, (void *)p->d_seg_curve,
+                  (void *)p->d_seg_tile0, (void *)p->d_dt, (void *)p->d_q, (void *)p->d_qw,
+                  (void *)p->d_counter, (void *)p->d_t, (void *)p->d_x, (void *)p->d_w,
+                  (void *)p->d_periods, (void *)p->d_sr, (void *)p->d_depth, (void *)p->d_j,
+                  (void *)p->d_k, (void *)p->d_best})
+    free_dev(d);
+  for (void *h : {(void *)p->h_curves, (void *)p->h_seg_start, (void *)p->h_seg_curve,
+                  (void *)p->h_seg_tile0})
+    if (h) (void)hipHostFree(h);
+  for (hipEvent_t ev : {p->ev_begin, p->ev_search0, p->ev_search1, p->ev_end})
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+  return BLS_OK;
+}
+
+int bls_search(bls_plan *p, const double *times, const double *flux, const double *weights,
+               int64_t n, const double *periods, int64_t nperiods, int32_t nbins, double qmin,
+               double qmax, double *sr, double *phase, double *duration, double *depth,
+               int32_t *jstart, int32_t *kwidth, int64_t *best_index) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (n < 0 || nperiods < 1)
+    return set_error(p, BLS_ERR_INVALID_ARG, "need n >= 2 and nperiods >= 1");
+  int64_t n_off[2] = {0, n};
+  bls_batch b;
+  memset(&b, 0, sizeof b);
+  b.ncurves = 1;
+  b.n_off = n_off;
+  b.times = times;
+  b.flux = flux;
+  b.weights = weights;
+  b.p_off = nullptr;
+  b.periods = periods;
+  b.nperiods_shared = nperiods;
+  b.nbins_all = nbins;
+  b.qmin_all = qmin;
+  b.qmax_all = qmax;
+  bls_results o{sr, phase, duration, depth, jstart, kwidth, best_index};
+  return bls_search_batch(p, &b, &o);
+}
+
+int bls_search_batch(bls_plan *p, const bls_batch *b, const bls_results *out) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!b || !out) return set_error(p, BLS_ERR_INVALID_ARG, "batch and out must be non-NULL");
+  p->last_error.clear();
+  std::string err;
+  int st = validate_batch(p->cfg, *b, true, p->shapes, err);
+  if (st != BLS_OK) return set_error(p, st, err);
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  return host_search(p, *b, p->shapes, *out);
+}
+
+int bls_search_device(bls_plan *p, const bls_batch *b, const bls_device_results *o) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!b || !o || !o->sr || !o->depth || !o->jstart || !o->kwidth || !o->best_index)
+    return set_error(p, BLS_ERR_INVALID_ARG, "batch and every device result array are required");
+  p->last_error.clear();
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  const bool use_graph = (p->cfg.flags & BLS_NO_GRAPH) == 0;
+  const uint64_t sig = batch_signature(p, *b, *o);
+  if (use_graph && p->graph_valid && sig == p->graph_sig) {
+    if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+    if ((e = hipGraphLaunch(p->gexec, p->stream)) != hipSuccess)
+      return hip_error(p, e, "graph launch");
+    if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+    p->search_timed = false;
+    fill_stats(p, p->last, true);
+    return BLS_OK;
+  }
+  std::string err;
+  int st = validate_batch(p->cfg, *b, false, p->shapes, err);
+  if (st != BLS_OK) return set_error(p, st, err);
+  const bool weighted = b->weights != nullptr;
+  TileChoice tc = choose_tiles(p, p->shapes, weighted);
+  PlannedBatch pb;
+  st = plan_batch(p, p->shapes, weighted, tc, pb);
+  if (st != BLS_OK) return st;
+  drop_graph(p);
+  p->last = pb;
+  if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+  if (use_graph) {
+    if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_error(p, e, "begin capture");
+    st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
+                        o->jstart, o->kwidth, o->best_index, false);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+    if (st != BLS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e2 != hipSuccess) return hip_error(p, e2, "end capture");
+    p->graph = g;
+    if ((e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      drop_graph(p);
+      return hip_error(p, e, "instantiate graph");
+    }
+    if ((e = hipGraphLaunch(p->gexec, p->stream)) != hipSuccess) {
+      drop_graph(p);
+      return hip_error(p, e, "graph launch");
+    }
+    p->graph_sig = sig;
+    p->graph_valid = true;
+    p->search_timed = false;
+  } else {
+    st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
+                        o->jstart, o->kwidth, o->best_index, true);
+    if (st != BLS_OK) return st;
+    p->search_timed = true;
+  }
+  if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+  fill_stats(p, pb, false);
+  return BLS_OK;
+}
+
+int bls_synchronize(bls_plan *p) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_error(p, e, "synchronize");
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, p->ev_begin, p->ev_end) == hipSuccess) p->stats.total_ms = ms;
+  if (p->search_timed && hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1) == hipSuccess)
+    p->stats.search_ms = ms;
+  else
+    p->stats.search_ms = p->stats.total_ms;
+  if (p->last.ncurves > 0) return check_device_status(p, p->last.ncurves);
+  return BLS_OK;
+}
+
+int bls_get_stream(const bls_plan *p, void **stream) {
+  if (!p || !stream) return BLS_ERR_INVALID_ARG;
+  *stream = (void *)p->stream;
+  return BLS_OK;
+}
+
+int bls_width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t *kmax) {
+  return width_range(nbins, qmin, qmax, kmin, kmax);
+}
+
+int bls_last_error(const bls_plan *p, char *buf, size_t len) {
+  if (!buf || len == 0) return BLS_ERR_INVALID_ARG;
+  const std::string &m = p ? p->last_error : g_create_error;
+  const size_t n = std::min(len - 1, m.size());
+  memcpy(buf, m.data(), n);
+  buf[n] = '\0';
+  return BLS_OK;
+}
+
+const char *bls_status_string(int status) {
+  switch (status) {
+    case BLS_OK: return "ok";
+    case BLS_ERR_INVALID_ARG: return "invalid argument";
+    case BLS_ERR_NO_MEMORY: return "out of memory";
+    case BLS_ERR_DEVICE: return "device (HIP) error";
+    case BLS_ERR_CAPACITY: return "exceeds plan capacity";
+    case BLS_ERR_BUSY: return "not ready";
+    case BLS_ERR_TIMEOUT: return "timed out";
+    default: return "unknown status";
+  }
+}
+
+int bls_last_stats(const bls_plan *p, bls_call_stats *out) {
+  if (!p || !out) return BLS_ERR_INVALID_ARG;
+  *out = p->stats;
+  return BLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Plan object and host-side planning shared by the C ABI, the autotuner and
+// the serving scheduler.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bls.h"
+#include "bls_device.h"
+
+namespace bls {
+
+// Launch shape chosen per batch (by the tuner or the built-in table).
+struct TileChoice {
+  int lds_budget = 32768;   // dynamic LDS bytes per workgroup to aim for
+  int tile_cap = kTileMax;  // upper bound on periods per work item
+  int occupancy = 0;        // workgroups per CU to launch (0 = max resident)
+};
+
+// A fully planned call: descriptors in pinned host memory, ready to upload.
+struct PlannedBatch {
+  int32_t ncurves = 0;
+  bool weighted = false;
+  int64_t total_points = 0;
+  int64_t total_results = 0;
+  int64_t nitems = 0;
+  int32_t nseg = 0;
+  int32_t hist_bytes = 0;
+  int32_t grid = 0;
+  double trial_points = 0.0;
+  double box_evals = 0.0;
+};
+
+// Per-curve shape after validation (host only).
+struct CurveShape {
+  int64_t n_off, n, p_off, r_off;
+  int32_t nperiods, nbins, kmin, kmax;
+};
+
+}  // namespace bls
+
+struct bls_plan {
+  bls_plan_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cus = 0;
+  int max_lds = 0;
+
+  // device working set
+  bls::CurveDesc *d_curves = nullptr;
+  int64_t *d_seg_start = nullptr;
+  int32_t *d_seg_curve = nullptr;
+  int32_t *d_seg_tile0 = nullptr;
+  double *d_dt = nullptr;
+  int32_t *d_q = nullptr;
+  int32_t *d_qw = nullptr;
+  unsigned long long *d_counter = nullptr;
+
+  // host-API staging (allocated on first use)
+  bool staging = false;
+  double *d_t = nullptr, *d_x = nullptr, *d_w = nullptr, *d_periods = nullptr;
+  float *d_sr = nullptr, *d_depth = nullptr;
+  int32_t *d_j = nullptr, *d_k = nullptr;
+  int64_t *d_best = nullptr;
+
+  // pinned host descriptors
+  bls::CurveDesc *h_curves = nullptr;
+  int64_t *h_seg_start = nullptr;
+  int32_t *h_seg_curve = nullptr;
+  int32_t *h_seg_tile0 = nullptr;
+
+  // graph cache for bls_search_device
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t graph_sig = 0;
+  bool graph_valid = false;
+
+  hipEvent_t ev_begin = nullptr, ev_search0 = nullptr, ev_search1 = nullptr,
+             ev_end = nullptr;
+  bool search_timed = false;
+
+  bls::PlannedBatch last;
+  bls_call_stats stats{};
+  std::string last_error;
+  std::vector<bls::CurveShape> shapes;   // scratch for planning
+  std::vector<int> order;                // scratch for planning
+  bool tuned_valid = false;
+  uint64_t tuned_key = 0;
+  bls::TileChoice tuned;
+};
+
+namespace bls {
+
+// Validation of a batch description and its parameters (host only; no
+// device access).  With check_data, also the host data arrays.
+int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
+                   std::vector<CurveShape> &shapes, std::string &err);
+
+// Fill the pinned descriptors for a validated batch and size the launch.
+int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
+               const TileChoice &tc, PlannedBatch &out);
+
+// Queue: upload descriptors, clear counters, prep, search, best index.
+int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
+                   const double *w, const double *periods, float *sr, float *depth,
+                   int32_t *js, int32_t *ks, int64_t *best, bool timed);
+
+int set_error(bls_plan *p, int status, const std::string &msg);
+int hip_error(bls_plan *p, hipError_t e, const char *what);
+int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t *kmax);
+
+// Device allocation with the optional failure-injection hook.
+hipError_t device_alloc(void **ptr, size_t bytes);
+
+// Tile choice for a batch: autotuned (cached) unless disabled.
+TileChoice choose_tiles(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted);
+// The built-in table the tuner starts from.
+TileChoice default_tiles(bool weighted);
+
+}  // namespace bls
