@@ -199,6 +199,17 @@ int bls_last_error(const bls_plan *plan, char *buf, size_t len);
 /* Static description of a status code. */
 const char *bls_status_string(int status);
 
+/*
+ * Diagnostic: the phase bin the search kernel assigns to each point of one
+ * curve (unit weights) at one trial period, computed by the same device
+ * code (t0 = min time, d = t - t0, f = 1/P, bin = min(trunc(frac(d f)
+ * nbins), nbins - 1), all FP64).  times: host [n], finite; bins: host [n]
+ * output.  Synchronous.  For checking bin-exact agreement with an FP64
+ * reference.  Errors: INVALID_ARG, CAPACITY (n above max_points), DEVICE.
+ */
+int bls_debug_phase_bins(bls_plan *plan, const double *times, int64_t n,
+                         double period, int32_t nbins, int32_t *bins);
+
 /* Timing and shape of the plan's last search call. */
 typedef struct {
     double search_ms;       /* search kernel, device time (HIP events)      */
@@ -213,6 +224,114 @@ typedef struct {
 } bls_call_stats;
 
 int bls_last_stats(const bls_plan *plan, bls_call_stats *out);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop with continuous batching.  Requests (one light curve with
+ * its own trial-period grid, bins and duty-cycle range) are queued by
+ * bls_server_submit, which copies the inputs and returns at once.  A
+ * scheduler thread admits queued requests while device memory (points and
+ * periods of the request arena) and slots are free, keeps every admitted
+ * curve resident on the device, and issues persistent launches ("ticks")
+ * that hold period tiles of all admitted requests at once: the oldest
+ * requests get most of each tick, and every admitted request gets at least
+ * one tile, so newly admitted work overlaps with work already running.  A
+ * request's results are identical to those of bls_search on the same input.
+ */
+typedef struct bls_server bls_server;
+
+typedef struct {
+    int32_t device;
+    int32_t max_slots;            /* requests resident on the device at once  */
+    int64_t arena_bytes;          /* device bytes for resident requests       */
+    int32_t max_nbins;            /* <= BLS_MAX_NBINS                          */
+    int32_t min_in_points;        /* as for a plan                             */
+    uint32_t flags;               /* BLS_DIP_ONLY                              */
+    int32_t reserved;
+    double tick_cost;             /* work per launch, in point-period units
+                                     (N*periods + 1.6*box evaluations); 0 = auto */
+    int64_t max_request_points;   /* largest N accepted (<= 2^24)              */
+    int64_t max_request_periods;  /* largest period grid accepted              */
+} bls_server_config;
+
+/* One request: host arrays, copied by bls_server_submit. */
+typedef struct {
+    const double *times;
+    const double *flux;
+    const double *weights;        /* NULL = unit weights */
+    int64_t n;
+    const double *periods;
+    int64_t nperiods;
+    int32_t nbins;
+    int32_t reserved;
+    double qmin;
+    double qmax;
+} bls_request;
+
+/* A finished request.  The arrays belong to the server and stay valid
+ * until bls_server_release(ticket). */
+typedef struct {
+    int32_t status;               /* BLS_OK or the request's error             */
+    int32_t reserved;
+    int64_t nperiods;
+    const float *sr;              /* [nperiods] SR                             */
+    const float *depth;           /* [nperiods] depth (NaN: no box)            */
+    const int32_t *jstart;        /* [nperiods] box start bin (-1: no box)     */
+    const int32_t *kwidth;        /* [nperiods] box width in bins (-1: none)   */
+    int64_t best_index;           /* first period with the largest SR          */
+    double submit_s;              /* server clock (s since creation)           */
+    double admit_s;
+    double done_s;
+} bls_result;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, queued, active, ticks;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> done, completed requests */
+    double trial_points;          /* sum N*nperiods of completed requests      */
+    double box_evals;             /* box evaluations of completed requests     */
+    double busy_s;                /* device time of the launches               */
+    double wall_s;                /* wall time since creation or reset         */
+    int64_t device_bytes_in_use;
+    int64_t device_bytes_peak;
+} bls_server_stats;
+
+/* Defaults: device 0, 256 slots, 4 GiB arena, max_nbins 4096, min_in_points
+ * 1, no flags, automatic tick size, N <= 2^20, nperiods <= 2^20. */
+void bls_server_config_init(bls_server_config *cfg);
+
+/* Allocate the arena and start the scheduler thread.  Errors: INVALID_ARG,
+ * NO_MEMORY, DEVICE (message via bls_server_last_error(NULL, ...)). */
+int bls_server_create(bls_server **out, const bls_server_config *cfg);
+
+/* Queue a request; non-blocking; inputs are copied.  *ticket identifies it.
+ * Errors (no ticket issued): INVALID_ARG (same checks as bls_search),
+ * CAPACITY (larger than the limits or than the whole arena). */
+int bls_server_submit(bls_server *srv, const bls_request *req, uint64_t *ticket);
+
+/* BUSY while the request is queued or running; BLS_OK with *out filled when
+ * done (out->status holds the request's own status); INVALID_ARG for an
+ * unknown or released ticket. */
+int bls_server_poll(bls_server *srv, uint64_t ticket, bls_result *out);
+
+/* As poll, but waits up to timeout_s seconds (TIMEOUT if still running). */
+int bls_server_wait(bls_server *srv, uint64_t ticket, bls_result *out,
+                    double timeout_s);
+
+/* Free a finished request's results; INVALID_ARG if unknown or not done. */
+int bls_server_release(bls_server *srv, uint64_t ticket);
+
+/* Counters and latency percentiles since creation or the last reset. */
+int bls_server_get_stats(bls_server *srv, bls_server_stats *out);
+int bls_server_reset_stats(bls_server *srv);
+
+/* Wait until no request is queued or running (TIMEOUT after timeout_s). */
+int bls_server_drain(bls_server *srv, double timeout_s);
+
+/* Message of the server's last error (srv NULL: of bls_server_create). */
+int bls_server_last_error(const bls_server *srv, char *buf, size_t len);
+
+/* Stop the scheduler (waiting for running launches) and free everything.
+ * NULL is accepted. */
+int bls_server_destroy(bls_server *srv);
 
 #ifdef __cplusplus
 }

@@ -22,13 +22,14 @@ from .api import (  # noqa: F401
     bls_last_error,
     bls_status_string,
     bls_last_stats,
+    bls_debug_phase_bins,
     bls_server_config_init,
     bls_server_create,
     bls_server_submit,
     bls_server_poll,
     bls_server_wait,
     bls_server_release,
-    bls_server_stats,
+    bls_server_get_stats,
     bls_server_reset_stats,
     bls_server_drain,
     bls_server_destroy,

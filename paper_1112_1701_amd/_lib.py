@@ -97,7 +97,8 @@ class BlsServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32),
                 ("arena_bytes", C.c_int64), ("max_nbins", C.c_int32),
                 ("min_in_points", C.c_int32), ("flags", C.c_uint32),
-                ("tick_items", C.c_int32), ("max_request_points", C.c_int64),
+                ("reserved", C.c_int32), ("tick_cost", C.c_double),
+                ("max_request_points", C.c_int64),
                 ("max_request_periods", C.c_int64)]
 
 
@@ -137,6 +138,7 @@ def load():
         "bls_last_error": (C.c_int, [P, P, C.c_size_t]),
         "bls_status_string": (C.c_char_p, [C.c_int]),
         "bls_last_stats": (C.c_int, [P, P]),
+        "bls_debug_phase_bins": (C.c_int, [P, P, I64, D, I32, P]),
     }
     optional = {
         "bls_server_config_init": (None, [P]),
@@ -145,7 +147,7 @@ def load():
         "bls_server_poll": (C.c_int, [P, C.c_uint64, P]),
         "bls_server_wait": (C.c_int, [P, C.c_uint64, P, D]),
         "bls_server_release": (C.c_int, [P, C.c_uint64]),
-        "bls_server_stats": (C.c_int, [P, P]),
+        "bls_server_get_stats": (C.c_int, [P, P]),
         "bls_server_reset_stats": (C.c_int, [P]),
         "bls_server_drain": (C.c_int, [P, D]),
         "bls_server_last_error": (C.c_int, [P, P, C.c_size_t]),

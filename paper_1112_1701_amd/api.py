@@ -93,6 +93,16 @@ def bls_last_stats(plan) -> dict:
     return {f: getattr(s, f) for f, _ in L.BlsCallStats._fields_}
 
 
+def bls_debug_phase_bins(plan, times, period: float, nbins: int):
+    """Phase bin the device assigns to each point at one period (diagnostic)."""
+    t = _f64(times)
+    out = np.empty(t.shape[0], np.int32)
+    _check(L.load().bls_debug_phase_bins(plan, _ptr(t), t.shape[0],
+                                         float(period), int(nbins),
+                                         _ptr(out)), plan)
+    return out
+
+
 # ------------------------------------------------------------------ search
 def bls_search(plan, times, flux, weights, periods, nbins, qmin, qmax):
     """One light curve in host memory; returns a dict of numpy arrays."""
@@ -311,9 +321,9 @@ def bls_server_release(srv, ticket: int) -> None:
         raise BlsError(st, _server_error(srv))
 
 
-def bls_server_stats(srv) -> dict:
+def bls_server_get_stats(srv) -> dict:
     s = L.BlsServerStats()
-    st = L.load().bls_server_stats(srv, C.byref(s))
+    st = L.load().bls_server_get_stats(srv, C.byref(s))
     if st != L.BLS_OK:
         raise BlsError(st, _server_error(srv))
     return {f: getattr(s, f) for f, _ in L.BlsServerStats._fields_}

@@ -22,6 +22,7 @@ enum CurveStatus : int32_t {
   kCurveOk = 0,
   kCurveBadData = 1,    // non-finite kept time/flux, bad weight
   kCurveTooFew = 2,     // fewer than two kept points or zero total weight
+  kCurveBadPeriod = 3,  // a trial period that is not finite and > 0
 };
 
 struct CurveDesc {
@@ -38,6 +39,8 @@ struct CurveDesc {
   int32_t shift;        // count field starts at this bit of a bin word
   int32_t qbits;        // magnitude bits of a point's fixed-point value
   int32_t weighted;     // 1 if a weight array is present
+  int32_t check_periods;  // 1: prep checks this curve's trial periods
+  int32_t pad0;
   // ---- written by the prep kernel
   double t0;            // min time over kept points
   double W;             // sum of weights (FP64)
@@ -53,6 +56,7 @@ struct CurveDesc {
 
 struct PrepArgs {
   CurveDesc *curves;
+  const double *periods;
   int32_t ncurves;
   const double *t;
   const double *x;
@@ -91,6 +95,9 @@ int launch_prep(const PrepArgs &a, void *stream);
 int launch_search(const SearchArgs &a, bool weighted, bool dip_only, int grid,
                   void *stream);
 int launch_best_index(unsigned long long *keys, int32_t n, void *stream);
+// Phase bin of every prepared point at one period (diagnostic).
+int launch_bins(const double *dt, int64_t n, const double *period, int32_t nbins, int32_t *bins,
+                void *stream);
 // Workgroups of the search kernel one CU holds at this LDS size.
 int search_blocks_per_cu(bool weighted, bool dip_only, int hist_bytes,
                          int *blocks);

@@ -124,14 +124,23 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
     sw = sw + wi;
     swx = swx + wi * xi;
   }
+  // Trial periods of this curve (device-side inputs are checked here).
+  long long badp = 0, unused0 = 0;
+  if (cd->check_periods) {
+    for (int64_t i = tid; i < cd->nperiods; i += kBlock) {
+      const double P = a.periods[cd->p_off + i];
+      if (!isfinite(P) || !(P > 0.0)) badp = 1;
+    }
+  }
+  block_isum2(badp, unused0, ia, ib);
   block_isum2(cnt, bad, ia, ib);
   block_sum2(sw, swx, sa, sb);
   double tmax_unused = -INFINITY;
   block_minmax(tmin, tmax_unused, sa, sb);
 
-  if (bad != 0 || cnt < 2 || !(sw > 0.0) || !isfinite(sw)) {
+  if (badp != 0 || bad != 0 || cnt < 2 || !(sw > 0.0) || !isfinite(sw)) {
     if (tid == 0) {
-      cd->status = bad ? kCurveBadData : kCurveTooFew;
+      cd->status = badp ? kCurveBadPeriod : bad ? kCurveBadData : kCurveTooFew;
       cd->n_eff = (int32_t)cnt;
     }
     // zero the encoded points so that no kernel reads garbage
@@ -198,24 +207,49 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
 }
 
 // ---------------------------------------------------------------- search
-// One bin word holds (count << shift) + sum of signed fixed-point values;
-// the sum needs fewer than shift - 1 bits, so it is the sign-extended low
-// field and the count is what remains above it.
-__device__ inline void decode_word(unsigned long long u, int shift, long long &sum,
-                                   unsigned long long &count) {
+// One bin word holds (count << shift) + sum of signed fixed-point values.
+// |sum| < 2^46 < 2^(shift - 1), so the sum is the sign-extended low field
+// and the count is what remains above it.
+struct BinWord {
+  long long sum;
+  unsigned count;
+};
+
+__device__ inline BinWord decode_word(unsigned long long u, int shift) {
+  BinWord w;
   const int hi = 64 - shift;
-  sum = ((long long)(u << hi)) >> hi;
-  count = (u - (unsigned long long)sum) >> shift;
+  w.sum = ((long long)(u << hi)) >> hi;
+  // a negative sum borrowed one from the count field
+  w.count = (unsigned)(u >> shift) - (unsigned)(w.sum >> 63);
+  return w;
 }
 
-// Phase bin with the FP64 operation order of the definition.
-__device__ inline int phase_bin(double d, double f, double nbd, int nbm1) {
+// Correctly rounded float of an integer with |v| < 2^47: both halves convert
+// exactly and the fused multiply-add rounds once.
+__device__ inline float int47_to_float(long long v) {
+  const int hi = (int)(v >> 24);
+  const unsigned lo = (unsigned)v & 0xFFFFFFu;
+  return fmaf((float)hi, 16777216.0f, (float)lo);
+}
+
+// trunc(frac(d f) nbins) with the FP64 operation order of the definition.
+// For finite c >= 0, c - floor(c) is exact and below 1, so v_fract_f64
+// returns exactly that value.  The result lies in [0, nbins]; nbins itself
+// (phase so close to 1 that the product rounds up) is the clamp case of the
+// definition.
+__device__ inline int raw_bin(double d, double f, double nbd) {
   const double c = d * f;
-  const double ph = c - floor(c);
-  const int b = (int)(ph * nbd);
-  return min(max(b, 0), nbm1);
+  const double ph = __builtin_amdgcn_fract(c);
+  return (int)(ph * nbd);
 }
 
+__device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
+  return (int)min((unsigned)raw_bin(d, f, nbd), nbm1);
+}
+
+// Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
+// Each period's histogram has nb + 1 words: the extra word catches the
+// clamp case and is added to bin nb - 1 when the histogram is decoded.
 template <bool WEIGHTED, bool FULL>
 __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int64_t base,
                                   int np, const double *s_f, unsigned long long *s_hist,
@@ -223,8 +257,7 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   const int tid = threadIdx.x;
   const int64_t off = cd.n_off;
   const int64_t n = cd.n;
-  const int nb = cd.nbins;
-  const double nbd = (double)nb;
+  const double nbd = (double)cd.nbins;
   const unsigned long long one = 1ull << cd.shift;
   double d[kPPT];
   unsigned long long va[kPPT];
@@ -256,7 +289,7 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
 #pragma unroll
     for (int r = 0; r < kPPT; ++r) {
       if (FULL || ok[r]) {
-        const int b = phase_bin(d[r], f, nbd, nb - 1);
+        const int b = raw_bin(d[r], f, nbd);
         __hip_atomic_fetch_add(h + b * wpb, va[r], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
         if (WEIGHTED)
@@ -267,16 +300,116 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   }
 }
 
-// (t, j) of a flattened index over np rows of nb entries.
-__device__ inline void split_index(int idx, int nb, float inv_nb, int &t, int &j) {
-  t = (int)((float)idx * inv_nb);
-  j = idx - t * nb;
-  if (j < 0) {
-    --t;
-    j += nb;
-  } else if (j >= nb) {
-    ++t;
-    j -= nb;
+// Exact test of one box against a lane's best (bn, bd): divide-free
+// comparison v > v_best, validity on exact counts, dip-only sign.
+template <bool WEIGHTED, bool DIP, bool MIP1>
+__device__ __forceinline__ void consider(float R, float S, float C, float d, int m, float nmax1,
+                                         float mipf, float &bn, float &bd, int &bm) {
+  const float num = S * S;
+  const float den = R * d;
+  bool ok = num * bd > bn * den;
+  if (WEIGHTED) {
+    ok = ok & (C <= nmax1) & (C >= mipf) & (den > 0.0f);
+  } else {
+    ok = ok & (d >= 1.0f);  // at least one point outside the box
+    if (!MIP1) ok = ok & (R >= mipf);
+  }
+  if (DIP) ok = ok & (S < 0.0f);
+  if (ok) {
+    bn = num;
+    bd = den;
+    bm = m;
+  }
+}
+
+// One lane task, unit weights: every width kmin..kmax from start bin j (h
+// points at bin j of the period's histogram; the wrap-around copy follows
+// the last bin).  Counts are exact integers in FP32, so d = W - R is kept
+// by subtraction and u = theta R by fused multiply-add; a box can beat
+// theta only if S^2 >= u d.  Boxes passing that screen get the exact test.
+template <bool DIP, bool MIP1>
+__device__ __forceinline__ void scan_task_unit(const float2 *h, int kmin, int kmax, float Wf,
+                                               float thr, float mipf, float &bn, float &bd,
+                                               int &bm) {
+  float d = Wf, S = 0.0f, u = 0.0f;
+  int m = 0;
+  for (; m < kmin - 1; ++m) {
+    const float2 e = h[m];
+    d -= e.x;
+    S += e.y;
+    u = fmaf(thr, e.x, u);
+  }
+  bn = 0.0f;
+  bd = 1.0f;
+  bm = -1;
+  for (; m + 4 <= kmax; m += 4) {
+    const float2 e0 = h[m], e1 = h[m + 1], e2 = h[m + 2], e3 = h[m + 3];
+    const float d0 = d - e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
+    const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
+    const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
+    const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
+    const bool p0 = S0 * S0 >= u0 * d0;
+    const bool p1 = S1 * S1 >= u1 * d1;
+    const bool p2 = S2 * S2 >= u2 * d2;
+    const bool p3 = S3 * S3 >= u3 * d3;
+    if (p0 | p1 | p2 | p3) {
+      if (p0) consider<false, DIP, MIP1>(Wf - d0, S0, 0.f, d0, m, 0.f, mipf, bn, bd, bm);
+      if (p1) consider<false, DIP, MIP1>(Wf - d1, S1, 0.f, d1, m + 1, 0.f, mipf, bn, bd, bm);
+      if (p2) consider<false, DIP, MIP1>(Wf - d2, S2, 0.f, d2, m + 2, 0.f, mipf, bn, bd, bm);
+      if (p3) consider<false, DIP, MIP1>(Wf - d3, S3, 0.f, d3, m + 3, 0.f, mipf, bn, bd, bm);
+    }
+    d = d3;
+    S = S3;
+    u = u3;
+  }
+  for (; m < kmax; ++m) {
+    const float2 e = h[m];
+    d -= e.x;
+    S += e.y;
+    u = fmaf(thr, e.x, u);
+    if (S * S >= u * d) consider<false, DIP, MIP1>(Wf - d, S, 0.f, d, m, 0.f, mipf, bn, bd, bm);
+  }
+}
+
+// One lane task, weighted curves: running sums of weight R, signal S and
+// count C; screen S^2 >= theta R (W - R).
+template <bool DIP>
+__device__ __forceinline__ void scan_task_weighted(const float4 *h, int kmin, int kmax, float Wf,
+                                                   float thr, float nmax1, float mipf, float &bn,
+                                                   float &bd, int &bm) {
+  float R = 0.0f, S = 0.0f, C = 0.0f;
+  int m = 0;
+  for (; m < kmin - 1; ++m) {
+    const float4 e = h[m];
+    R += e.x;
+    S += e.y;
+    C += e.z;
+  }
+  bn = 0.0f;
+  bd = 1.0f;
+  bm = -1;
+  for (; m + 2 <= kmax; m += 2) {
+    const float4 e0 = h[m], e1 = h[m + 1];
+    const float R0 = R + e0.x, S0 = S + e0.y, C0 = C + e0.z;
+    const float R1 = R0 + e1.x, S1 = S0 + e1.y, C1 = C0 + e1.z;
+    const float d0 = Wf - R0, d1 = Wf - R1;
+    const bool p0 = S0 * S0 >= thr * (R0 * d0);
+    const bool p1 = S1 * S1 >= thr * (R1 * d1);
+    if (p0 | p1) {
+      if (p0) consider<true, DIP, false>(R0, S0, C0, d0, m, nmax1, mipf, bn, bd, bm);
+      if (p1) consider<true, DIP, false>(R1, S1, C1, d1, m + 1, nmax1, mipf, bn, bd, bm);
+    }
+    R = R1;
+    S = S1;
+    C = C1;
+  }
+  for (; m < kmax; ++m) {
+    const float4 e = h[m];
+    R += e.x;
+    S += e.y;
+    C += e.z;
+    const float d = Wf - R;
+    if (S * S >= thr * (R * d)) consider<true, DIP, false>(R, S, C, d, m, nmax1, mipf, bn, bd, bm);
   }
 }
 
@@ -336,14 +469,10 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const int nb = cd.nbins;
     const int kmin = cd.kmin;
     const int kmax = cd.kmax;
-    const int HB = nb + kmax - 1;  // bins plus the wrap-around copy
+    const int HB = nb + max(kmax - 1, 1);  // bins, then clamp word / wrap copy
 
     // Clear the tile's histograms; frequencies f = 1/P (IEEE division).
-    for (int i = tid; i < np * nb * wpb; i += kBlock) {
-      int t, b;
-      split_index(i / wpb, nb, 1.0f / (float)nb, t, b);
-      s_hist[((size_t)t * HB + b) * wpb + (i % wpb)] = 0ull;
-    }
+    for (int i = tid; i < np * HB * wpb; i += kBlock) s_hist[i] = 0ull;
     if (tid < np) {
       s_f[tid] = 1.0 / a.periods[cd.p_off + p0 + tid];
       s_best[tid] = 0ull;
@@ -359,33 +488,43 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     }
     __syncthreads();
 
-    // Exact integer bins -> FP32 (count, sum) in place.
-    const float inv_nb = 1.0f / (float)nb;
-    const float qscale = ldexpf(1.0f, -cd.qbits);
-    for (int i = tid; i < np * nb; i += kBlock) {
-      int t, b;
-      split_index(i, nb, inv_nb, t, b);
-      unsigned long long *w = s_hist + ((size_t)t * HB + b) * wpb;
-      long long sa;
-      unsigned long long ca;
-      decode_word(w[0], cd.shift, sa, ca);
-      if (WEIGHTED) {
-        const long long sb = (long long)w[1];
-        float4 *o = reinterpret_cast<float4 *>(w);
-        *o = make_float4((float)sa * qscale, (float)sb * qscale, (float)ca, 0.0f);
-      } else {
-        float2 *o = reinterpret_cast<float2 *>(w);
-        *o = make_float2((float)ca, (float)sa * qscale);
+    // Exact integer bins -> FP32 in place (the clamp word joins bin nb - 1).
+    {
+      const float qscale = ldexpf(1.0f, -cd.qbits);
+      int t = tid / nb, b = tid - (tid / nb) * nb;
+      const int dt = kBlock / nb, db = kBlock - (kBlock / nb) * nb;
+      for (; t < np;) {
+        unsigned long long *w = s_hist + ((size_t)t * HB + b) * wpb;
+        unsigned long long w0 = w[0];
+        unsigned long long w1 = WEIGHTED ? w[1] : 0ull;
+        if (b == nb - 1) {
+          w0 += w[wpb];
+          if (WEIGHTED) w1 += w[wpb + 1];
+        }
+        const BinWord bw = decode_word(w0, cd.shift);
+        if (WEIGHTED) {
+          float4 *o = reinterpret_cast<float4 *>(w);
+          *o = make_float4(int47_to_float(bw.sum) * qscale,
+                           int47_to_float((long long)w1) * qscale, (float)bw.count, 0.0f);
+        } else {
+          float2 *o = reinterpret_cast<float2 *>(w);
+          *o = make_float2((float)bw.count, int47_to_float(bw.sum) * qscale);
+        }
+        t += dt;
+        b += db;
+        if (b >= nb) {
+          b -= nb;
+          ++t;
+        }
       }
     }
     __syncthreads();
     // Wrap-around: bins 0 .. kmax-2 repeated after bin nb-1.
     if (kmax > 1) {
       const int ext = kmax - 1;
-      const float inv_ext = 1.0f / (float)ext;
       for (int i = tid; i < np * ext; i += kBlock) {
-        int t, e;
-        split_index(i, ext, inv_ext, t, e);
+        const int t = i / ext;
+        const int e = i - t * ext;
         unsigned long long *src = s_hist + ((size_t)t * HB + e) * wpb;
         unsigned long long *dst = s_hist + ((size_t)t * HB + nb + e) * wpb;
         dst[0] = src[0];
@@ -394,84 +533,49 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     }
     __syncthreads();
 
-    // Box scan: lane task = (period t, start bin j); running sums over widths.
-    const float Wf = cd.Wf;
-    const float nmax1 = (float)(cd.n_eff - 1);
-    const float mipf = (float)a.min_in_points;
-    const bool mip1 = a.min_in_points <= 1;
-    for (int task = tid; task < np * nb; task += kBlock) {
-      int t, j;
-      split_index(task, nb, inv_nb, t, j);
-      float R = 0.0f, S = 0.0f, C = 0.0f;
-      float bn = 0.0f, bd = 1.0f;
-      int bm = -1;
-      if (WEIGHTED) {
-        const float4 *h = reinterpret_cast<const float4 *>(s_hist) + (size_t)t * HB + j;
-        int m = 0;
-        for (; m < kmin - 1; ++m) {
-          const float4 e = h[m];
-          R += e.x;
-          S += e.y;
-          C += e.z;
-        }
-        for (; m < kmax; ++m) {
-          const float4 e = h[m];
-          R += e.x;
-          S += e.y;
-          C += e.z;
-          const float den = R * (Wf - R);
-          const float num = S * S;
-          bool better = (num * bd > bn * den) & (C <= nmax1) & (C >= mipf) & (den > 0.0f);
-          if (DIP) better &= (S < 0.0f);
-          bn = better ? num : bn;
-          bd = better ? den : bd;
-          bm = better ? m : bm;
-        }
-      } else {
-        const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
-        int m = 0;
-        for (; m < kmin - 1; ++m) {
-          const float2 e = h[m];
-          R += e.x;
-          S += e.y;
-        }
-        if (mip1) {
-          for (; m < kmax; ++m) {
-            const float2 e = h[m];
-            R += e.x;
-            S += e.y;
-            const float dd = Wf - R;
-            const float den = R * dd;
-            const float num = S * S;
-            bool better = (num * bd > bn * den) & (dd >= 1.0f);
-            if (DIP) better &= (S < 0.0f);
-            bn = better ? num : bn;
-            bd = better ? den : bd;
-            bm = better ? m : bm;
-          }
+    // Box scan.  Lane task = (start bin j, period t), start-bin major, so that
+    // the per-period best found by earlier tasks (s_best) is already a good
+    // lower bound theta when later tasks run.  Boxes are screened against a
+    // slightly relaxed theta; only those that pass get the exact comparison,
+    // validity test and index bookkeeping.  The largest box always passes,
+    // so the result is that of the full comparison.
+    {
+      const float Wf = cd.Wf;
+      const float nmax1 = (float)(cd.n_eff - 1);
+      const float mipf = (float)a.min_in_points;
+      const bool mip1 = a.min_in_points <= 1;
+      int j = tid / np, t = tid - (tid / np) * np;
+      const int dj = kBlock / np, dtt = kBlock - (kBlock / np) * np;
+      for (; j < nb;) {
+        const float theta = __uint_as_float((unsigned)(s_best[t] >> 32));
+        const float thr = theta * (1.0f - 0x1p-14f);
+        float bn, bd;
+        int bm;
+        if (WEIGHTED) {
+          const float4 *h = reinterpret_cast<const float4 *>(s_hist) + (size_t)t * HB + j;
+          scan_task_weighted<DIP>(h, kmin, kmax, Wf, thr, nmax1, mipf, bn, bd, bm);
         } else {
-          for (; m < kmax; ++m) {
-            const float2 e = h[m];
-            R += e.x;
-            S += e.y;
-            const float dd = Wf - R;
-            const float den = R * dd;
-            const float num = S * S;
-            bool better = (num * bd > bn * den) & (dd >= 1.0f) & (R >= mipf);
-            if (DIP) better &= (S < 0.0f);
-            bn = better ? num : bn;
-            bd = better ? den : bd;
-            bm = better ? m : bm;
-          }
+          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
+          if (mip1)
+            scan_task_unit<DIP, true>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
+          else
+            scan_task_unit<DIP, false>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
         }
-      }
-      (void)C;
-      if (bm >= 0) {
-        const float v = bn / bd;
-        const unsigned idx = (unsigned)((bm + 1) * nb + j);
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
-        __hip_atomic_fetch_max(&s_best[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (bm >= 0) {
+          // Key: value (any consistent rounding; exact ties compare equal),
+          // then the smaller width and start.
+          const float v = bn * __builtin_amdgcn_rcpf(bd);
+          const unsigned idx = (unsigned)((bm + 1) * nb + j);
+          const unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                                         (unsigned long long)(0xFFFFFFFFu - idx);
+          __hip_atomic_fetch_max(&s_best[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        t += dtt;
+        j += dj;
+        if (t >= np) {
+          t -= np;
+          ++j;
+        }
       }
     }
     __syncthreads();
@@ -492,6 +596,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         const unsigned idx = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
         const int k = (int)(idx / (unsigned)nb);
         const int j = (int)(idx - (unsigned)k * (unsigned)nb);
+        // S in the scan's order; R (exact counts for unit weights)
         float R = 0.0f, S = 0.0f;
         if (WEIGHTED) {
           const float4 *h = reinterpret_cast<const float4 *>(s_hist) + (size_t)t * HB + j;
@@ -507,10 +612,10 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
           }
         }
         const double Rd = (double)R;
-        const double den = Rd * ((double)Wf - Rd);
+        const double den = Rd * ((double)cd.Wf - Rd);
         const double Sd = (double)S;
         const double sr = sqrt(Sd * Sd / den) * cd.out_scale;
-        const double depth = -Sd * (double)Wf / den * cd.out_scale;
+        const double depth = -Sd * (double)cd.Wf / den * cd.out_scale;
         srf = (float)sr;
         a.sr[r] = srf;
         a.depth[r] = (float)depth;
@@ -522,6 +627,15 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
       __hip_atomic_fetch_max(a.best_key + c, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
+  }
+}
+
+__global__ void bins_kernel(const double *dt, int64_t n, const double *period, int32_t nbins,
+                            int32_t *bins) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double f = 1.0 / period[0];
+    bins[i] = phase_bin(dt[i], f, (double)nbins, (unsigned)(nbins - 1));
   }
 }
 
@@ -574,6 +688,14 @@ int launch_search(const SearchArgs &a, bool weighted, bool dip_only, int grid, v
   e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)a.hist_bytes,
                       (hipStream_t)stream);
   if (e != hipSuccess) return (int)e;
+  return (int)hipGetLastError();
+}
+
+int launch_bins(const double *dt, int64_t n, const double *period, int32_t nbins, int32_t *bins,
+                void *stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(bins_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, dt, n, period, nbins, bins);
   return (int)hipGetLastError();
 }
 

@@ -249,6 +249,8 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
     d.shift = 64 - cb;
     d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
     d.weighted = weighted ? 1 : 0;
+    // each distinct period range is checked once (a shared grid by curve 0)
+    d.check_periods = (c == 0 || s.p_off != shapes[0].p_off) ? 1 : 0;
     const int per_period = (s.nbins + s.kmax - 1) * 8 * wpb;
     int T = std::max(1, tc.lds_budget / per_period);
     T = std::min(T, std::min(tc.tile_cap, kTileMax));
@@ -323,6 +325,7 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
 
   PrepArgs pa;
   pa.curves = p->d_curves;
+  pa.periods = periods;
   pa.ncurves = nc;
   pa.t = t;
   pa.x = x;
@@ -429,6 +432,8 @@ int check_device_status(bls_plan *p, int ncurves) {
       snprintf(msg, sizeof msg, "curve %d: %s", c,
                cds[c].status == kCurveBadData
                    ? "non-finite time/flux of a kept point, or a negative/non-finite weight"
+               : cds[c].status == kCurveBadPeriod
+                   ? "a trial period is not finite and > 0"
                    : "fewer than two points with positive weight");
       return set_error(p, BLS_ERR_INVALID_ARG, msg);
     }
@@ -750,6 +755,53 @@ int bls_search_device(bls_plan *p, const bls_batch *b, const bls_device_results 
   }
   if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   fill_stats(p, pb, false);
+  return BLS_OK;
+}
+
+int bls_debug_phase_bins(bls_plan *p, const double *times, int64_t n, double period,
+                         int32_t nbins, int32_t *bins) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!times || !bins || n < 2 || !isfinite(period) || !(period > 0.0) || nbins < 2)
+    return set_error(p, BLS_ERR_INVALID_ARG, "need times, bins, n >= 2, period > 0, nbins >= 2");
+  if (n > p->cfg.max_points || n > (int64_t(1) << 24))
+    return set_error(p, BLS_ERR_CAPACITY, "n exceeds the plan's max_points");
+  for (int64_t i = 0; i < n; ++i)
+    if (!isfinite(times[i])) return set_error(p, BLS_ERR_INVALID_ARG, "non-finite time");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  int st = ensure_staging(p);
+  if (st != BLS_OK) return st;
+  p->graph_valid = false;
+  CurveDesc &d = p->h_curves[0];
+  memset(&d, 0, sizeof d);
+  d.n = n;
+  d.nperiods = 1;
+  d.nbins = nbins;
+  const int cb = cbits_of(n);
+  d.shift = 64 - cb;
+  d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
+  hipStream_t s = p->stream;
+  if ((e = hipMemcpyAsync(p->d_curves, p->h_curves, sizeof(CurveDesc), hipMemcpyHostToDevice,
+                          s)) != hipSuccess ||
+      (e = hipMemcpyAsync(p->d_t, times, n * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(p->d_periods, &period, 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(p, e, "upload");
+  PrepArgs pa;
+  pa.curves = p->d_curves;
+  pa.periods = p->d_periods;
+  pa.ncurves = 1;
+  pa.t = p->d_t;
+  pa.x = p->d_t;  // any finite flux: only the time offsets are used
+  pa.w = nullptr;
+  pa.dt = p->d_dt;
+  pa.q = p->d_q;
+  pa.qw = p->d_qw;
+  if ((e = (hipError_t)launch_prep(pa, s)) != hipSuccess) return hip_error(p, e, "launch prep");
+  if ((e = (hipError_t)launch_bins(p->d_dt, n, p->d_periods, nbins, p->d_j, s)) != hipSuccess)
+    return hip_error(p, e, "launch bins");
+  if ((e = hipMemcpyAsync(bins, p->d_j, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_error(p, e, "download bins");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(p, e, "synchronize");
   return BLS_OK;
 }
 

@@ -1,0 +1,747 @@
+// Serving loop of the BLS library: requests are admitted by device memory,
+// stay resident on the device, and are searched by persistent launches
+// ("ticks") that mix period tiles of every admitted request (continuous
+// batching).  The arithmetic is the search kernel's, so a request's results
+// equal those of bls_search on the same input.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "bls_plan.h"
+#include "bls_sched.h"
+
+namespace bls {
+namespace {
+
+constexpr int kTickBuffers = 2;          // launches in flight
+constexpr int64_t kPeriodsPerPoint = 12; // arena split: period slots per point slot
+constexpr size_t kArenaAlign = 64;       // elements
+
+thread_local std::string g_server_create_error;
+
+struct Req {
+  uint64_t ticket = 0;
+  std::vector<double> t, x, w, per;
+  bool weighted = false;
+  int32_t nbins = 0, kmin = 0, kmax = 0;
+  int64_t n = 0, np = 0;
+  double submit_s = 0, admit_s = 0, done_s = 0;
+  int status = BLS_ERR_BUSY;
+  bool finished = false;
+  std::vector<float> sr, depth;
+  std::vector<int32_t> js, ks;
+  int64_t best = -1;
+  int slot = -1;
+  size_t pt_off = 0, pr_off = 0;
+  int32_t tile = 1, ntiles = 0, issued = 0, done_tiles = 0;
+  double item_cost = 0;
+  uint64_t order = 0;
+  double pp = 0, evals = 0;
+};
+
+struct Tick {
+  int buf = 0;
+  bool weighted = false;
+  std::vector<TickSegment> segs;
+};
+
+int cbits_of(int64_t n) {
+  int b = 0;
+  while (b < 63 && (int64_t(1) << b) <= n) ++b;
+  return b;
+}
+
+}  // namespace
+}  // namespace bls
+
+using namespace bls;
+
+struct bls_server {
+  bls_server_config cfg{};
+  int device = 0;
+  int num_cus = 0;
+  int max_lds = 0;
+  hipStream_t stream = nullptr, copy_stream = nullptr;
+
+  int64_t cap_pts = 0, cap_per = 0;
+  double *d_t = nullptr, *d_x = nullptr, *d_w = nullptr, *d_dt = nullptr, *d_per = nullptr;
+  int32_t *d_q = nullptr, *d_qw = nullptr, *d_js = nullptr, *d_ks = nullptr;
+  float *d_sr = nullptr, *d_depth = nullptr;
+  CurveDesc *d_curves = nullptr, *h_curves = nullptr;
+  unsigned long long *d_keys = nullptr;
+  int64_t *d_seg_start[kTickBuffers] = {}, *h_seg_start[kTickBuffers] = {};
+  int32_t *d_seg_curve[kTickBuffers] = {}, *h_seg_curve[kTickBuffers] = {};
+  int32_t *d_seg_tile0[kTickBuffers] = {}, *h_seg_tile0[kTickBuffers] = {};
+  unsigned long long *d_counter[kTickBuffers] = {};
+  hipEvent_t ev_s[kTickBuffers] = {}, ev_e[kTickBuffers] = {};
+  bool buf_busy[kTickBuffers] = {};
+
+  Arena pts_arena, per_arena;
+  std::vector<Req *> slots;
+  std::deque<Req *> pending;
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::deque<Tick> inflight;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread thr;
+  bool stop = false;
+  uint64_t next_ticket = 1, next_order = 1;
+
+  int64_t submitted = 0, admitted = 0, completed = 0, failed = 0, ticks = 0;
+  double pp_done = 0, evals_done = 0, busy_s = 0;
+  std::chrono::steady_clock::time_point t0, t_reset;
+  LatencyLog lat;
+  std::string last_error;
+  int lds_budget = 32768;
+  double tick_cost = 0;
+  int device_error = 0;
+};
+
+namespace {
+
+double now_s(const bls_server *s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+int srv_error(bls_server *s, int st, const std::string &msg) {
+  if (s)
+    s->last_error = msg;
+  else
+    g_server_create_error = msg;
+  return st;
+}
+
+int srv_hip(bls_server *s, hipError_t e, const char *what) {
+  return srv_error(s, e == hipErrorOutOfMemory ? BLS_ERR_NO_MEMORY : BLS_ERR_DEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Fail every unfinished request (device error in the scheduler).
+void fail_all(bls_server *s, int st) {
+  for (auto &kv : s->reqs) {
+    Req *r = kv.second.get();
+    if (!r->finished) {
+      r->finished = true;
+      r->status = st;
+      r->done_s = now_s(s);
+      s->failed++;
+    }
+  }
+  s->pending.clear();
+  for (auto &sl : s->slots) sl = nullptr;
+  s->cv_done.notify_all();
+}
+
+// Device work for a newly admitted request: inputs, descriptor, prep, key.
+hipError_t start_request(bls_server *s, Req *r) {
+  CurveDesc &d = s->h_curves[r->slot];
+  memset(&d, 0, sizeof d);
+  d.n_off = (int64_t)r->pt_off;
+  d.n = r->n;
+  d.p_off = (int64_t)r->pr_off;
+  d.r_off = (int64_t)r->pr_off;
+  d.nperiods = (int32_t)r->np;
+  d.nbins = r->nbins;
+  d.kmin = r->kmin;
+  d.kmax = r->kmax;
+  d.tile = r->tile;
+  const int cb = cbits_of(r->n);
+  d.shift = 64 - cb;
+  d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
+  d.weighted = r->weighted ? 1 : 0;
+  d.check_periods = 0;  // checked on the host at submit
+  hipStream_t st = s->stream;
+  hipError_t e;
+  const size_t n = (size_t)r->n, np = (size_t)r->np;
+  if ((e = hipMemcpyAsync(s->d_t + r->pt_off, r->t.data(), n * 8, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(s->d_x + r->pt_off, r->x.data(), n * 8, hipMemcpyHostToDevice, st)) ||
+      (r->weighted &&
+       (e = hipMemcpyAsync(s->d_w + r->pt_off, r->w.data(), n * 8, hipMemcpyHostToDevice, st))) ||
+      (e = hipMemcpyAsync(s->d_per + r->pr_off, r->per.data(), np * 8, hipMemcpyHostToDevice,
+                          st)) ||
+      (e = hipMemcpyAsync(s->d_curves + r->slot, &d, sizeof d, hipMemcpyHostToDevice, st)))
+    return e;
+  if ((e = (hipError_t)launch_fill(nullptr, s->d_keys + r->slot, 1, st))) return e;
+  PrepArgs pa;
+  pa.curves = s->d_curves + r->slot;
+  pa.periods = s->d_per;
+  pa.ncurves = 1;
+  pa.t = s->d_t;
+  pa.x = s->d_x;
+  pa.w = r->weighted ? s->d_w : nullptr;
+  pa.dt = s->d_dt;
+  pa.q = s->d_q;
+  pa.qw = s->d_qw;
+  return (hipError_t)launch_prep(pa, st);
+}
+
+hipError_t launch_tick(bls_server *s, Tick &tk) {
+  const int b = tk.buf;
+  int64_t items = 0;
+  int hist_bytes = 0;
+  const int wpb = tk.weighted ? 2 : 1;
+  for (size_t i = 0; i < tk.segs.size(); ++i) {
+    const TickSegment &g = tk.segs[i];
+    s->h_seg_start[b][i] = items;
+    s->h_seg_curve[b][i] = g.slot;
+    s->h_seg_tile0[b][i] = g.tile0;
+    items += g.ntiles;
+    const Req *r = s->slots[g.slot];
+    hist_bytes = std::max(hist_bytes, r->tile * (r->nbins + std::max(r->kmax - 1, 1)) * 8 * wpb);
+  }
+  const int nseg = (int)tk.segs.size();
+  s->h_seg_start[b][nseg] = items;
+  hipStream_t st = s->stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(s->d_seg_start[b], s->h_seg_start[b], 8 * (nseg + 1),
+                          hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(s->d_seg_curve[b], s->h_seg_curve[b], 4 * nseg, hipMemcpyHostToDevice,
+                          st)) ||
+      (e = hipMemcpyAsync(s->d_seg_tile0[b], s->h_seg_tile0[b], 4 * nseg, hipMemcpyHostToDevice,
+                          st)))
+    return e;
+  if ((e = (hipError_t)launch_fill(s->d_counter[b], nullptr, 0, st))) return e;
+  SearchArgs a;
+  a.curves = s->d_curves;
+  a.periods = s->d_per;
+  a.dt = s->d_dt;
+  a.q = s->d_q;
+  a.qw = tk.weighted ? s->d_qw : nullptr;
+  a.seg_start = s->d_seg_start[b];
+  a.seg_curve = s->d_seg_curve[b];
+  a.seg_tile0 = s->d_seg_tile0[b];
+  a.nseg = nseg;
+  a.min_in_points = s->cfg.min_in_points;
+  a.nitems = items;
+  a.counter = s->d_counter[b];
+  a.sr = s->d_sr;
+  a.depth = s->d_depth;
+  a.jstart = s->d_js;
+  a.kwidth = s->d_ks;
+  a.best_key = s->d_keys;
+  a.hist_bytes = hist_bytes;
+  const bool dip = (s->cfg.flags & BLS_DIP_ONLY) != 0;
+  int per_cu = 1;
+  if ((e = (hipError_t)search_blocks_per_cu(tk.weighted, dip, hist_bytes, &per_cu))) return e;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)s->num_cus *
+                                                                          std::max(per_cu, 1)));
+  if ((e = hipEventRecord(s->ev_s[b], st))) return e;
+  if ((e = (hipError_t)launch_search(a, tk.weighted, dip, (int)grid, st))) return e;
+  return hipEventRecord(s->ev_e[b], st);
+}
+
+// Copy a finished request's results to the host (the tick that completed
+// its last tile has finished, so nothing on the device still writes them).
+hipError_t collect_request(bls_server *s, Req *r) {
+  const size_t np = (size_t)r->np;
+  r->sr.resize(np);
+  r->depth.resize(np);
+  r->js.resize(np);
+  r->ks.resize(np);
+  unsigned long long key = 0;
+  CurveDesc cd;
+  hipStream_t cs = s->copy_stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(r->sr.data(), s->d_sr + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipMemcpyAsync(r->depth.data(), s->d_depth + r->pr_off, np * 4, hipMemcpyDeviceToHost,
+                          cs)) ||
+      (e = hipMemcpyAsync(r->js.data(), s->d_js + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipMemcpyAsync(r->ks.data(), s->d_ks + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipMemcpyAsync(&key, s->d_keys + r->slot, 8, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipMemcpyAsync(&cd, s->d_curves + r->slot, sizeof cd, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipStreamSynchronize(cs)))
+    return e;
+  r->best = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+  r->status = cd.status == kCurveOk ? BLS_OK : BLS_ERR_INVALID_ARG;
+  return hipSuccess;
+}
+
+void scheduler(bls_server *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  int next_buf = 0;
+  while (!s->stop) {
+    bool progressed = false;
+
+    // 1. Completed ticks: count tiles, finish requests, free their memory.
+    while (!s->inflight.empty()) {
+      Tick &tk = s->inflight.front();
+      hipError_t q = hipEventQuery(s->ev_e[tk.buf]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) {
+        s->device_error = BLS_ERR_DEVICE;
+        srv_hip(s, q, "search launch");
+        fail_all(s, BLS_ERR_DEVICE);
+        s->inflight.clear();
+        break;
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, s->ev_s[tk.buf], s->ev_e[tk.buf]) == hipSuccess)
+        s->busy_s += ms * 1e-3;
+      std::vector<Req *> done;
+      for (const TickSegment &g : tk.segs) {
+        Req *r = s->slots[g.slot];
+        if (!r) continue;
+        r->done_tiles += g.ntiles;
+        if (r->done_tiles == r->ntiles) done.push_back(r);
+      }
+      s->buf_busy[tk.buf] = false;
+      s->inflight.pop_front();
+      for (Req *r : done) {
+        lk.unlock();
+        hipError_t e = collect_request(s, r);
+        lk.lock();
+        if (e != hipSuccess) {
+          srv_hip(s, e, "collect results");
+          fail_all(s, BLS_ERR_DEVICE);
+          break;
+        }
+        r->done_s = now_s(s);
+        r->finished = true;
+        s->slots[r->slot] = nullptr;
+        s->pts_arena.release(r->pt_off);
+        s->per_arena.release(r->pr_off);
+        if (r->status == BLS_OK) {
+          s->completed++;
+          s->pp_done += r->pp;
+          s->evals_done += r->evals;
+          s->lat.add((r->done_s - r->submit_s) * 1e3);
+        } else {
+          s->failed++;
+        }
+      }
+      if (!done.empty()) s->cv_done.notify_all();
+      progressed = true;
+    }
+    if (s->device_error) break;
+
+    // 2. Admission, oldest first, while a slot and arena room are free.
+    std::vector<Req *> admitted;
+    while (!s->pending.empty()) {
+      Req *r = s->pending.front();
+      int slot = -1;
+      for (int i = 0; i < (int)s->slots.size(); ++i)
+        if (!s->slots[i]) {
+          slot = i;
+          break;
+        }
+      if (slot < 0) break;
+      const size_t po = s->pts_arena.alloc((size_t)r->n);
+      if (po == Arena::kFail) break;
+      const size_t pr = s->per_arena.alloc((size_t)r->np);
+      if (pr == Arena::kFail) {
+        s->pts_arena.release(po);
+        break;
+      }
+      r->slot = slot;
+      r->pt_off = po;
+      r->pr_off = pr;
+      r->admit_s = now_s(s);
+      r->order = s->next_order++;
+      s->slots[slot] = r;
+      s->pending.pop_front();
+      s->admitted++;
+      admitted.push_back(r);
+    }
+
+    // 3. Next launch if a buffer is free and tiles remain.
+    bool have_tick = false;
+    Tick tk;
+    if (!s->buf_busy[next_buf]) {
+      std::vector<SlotWork> work;
+      bool weighted = false, first = true;
+      uint64_t oldest = ~0ull;
+      for (Req *r : s->slots)
+        if (r && r->issued < r->ntiles && r->order < oldest) {
+          oldest = r->order;
+          weighted = r->weighted;
+          first = false;
+        }
+      if (!first) {
+        for (int i = 0; i < (int)s->slots.size(); ++i) {
+          Req *r = s->slots[i];
+          if (r && r->issued < r->ntiles && r->weighted == weighted)
+            work.push_back({i, r->order, r->ntiles, r->issued, r->item_cost});
+        }
+        tk.buf = next_buf;
+        tk.weighted = weighted;
+        tk.segs = build_tick(work, s->tick_cost, 1);
+        for (const SlotWork &wk : work) s->slots[wk.slot]->issued = wk.next_tile;
+        have_tick = !tk.segs.empty();
+      }
+    }
+
+    // Device work outside the lock (requests and slots stay put: only this
+    // thread frees them).
+    if (!admitted.empty() || have_tick) {
+      lk.unlock();
+      hipError_t e = hipSuccess;
+      for (Req *r : admitted)
+        if (e == hipSuccess) e = start_request(s, r);
+      if (e == hipSuccess && have_tick) e = launch_tick(s, tk);
+      lk.lock();
+      if (e != hipSuccess) {
+        s->device_error = BLS_ERR_DEVICE;
+        srv_hip(s, e, "enqueue");
+        fail_all(s, BLS_ERR_DEVICE);
+        break;
+      }
+      if (have_tick) {
+        s->buf_busy[tk.buf] = true;
+        s->inflight.push_back(std::move(tk));
+        s->ticks++;
+        next_buf = (next_buf + 1) % kTickBuffers;
+      }
+      progressed = true;
+    }
+
+    if (!progressed) {
+      if (s->inflight.empty())
+        s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      else
+        s->cv_work.wait_for(lk, std::chrono::microseconds(50));
+    }
+  }
+  lk.unlock();
+  (void)hipStreamSynchronize(s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+void bls_server_config_init(bls_server_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->device = 0;
+  cfg->max_slots = 256;
+  cfg->arena_bytes = int64_t(4) << 30;
+  cfg->max_nbins = BLS_MAX_NBINS;
+  cfg->min_in_points = 1;
+  cfg->flags = 0;
+  cfg->tick_cost = 0.0;
+  cfg->max_request_points = int64_t(1) << 20;
+  cfg->max_request_periods = int64_t(1) << 20;
+}
+
+int bls_server_destroy(bls_server *s);
+
+int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
+  if (!out) return srv_error(nullptr, BLS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  bls_server_config cfg;
+  if (cfg_in)
+    cfg = *cfg_in;
+  else
+    bls_server_config_init(&cfg);
+  if (cfg.min_in_points <= 0) cfg.min_in_points = 1;
+  if (cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.arena_bytes < (1 << 20) ||
+      cfg.max_nbins < 2 || cfg.max_nbins > BLS_MAX_NBINS || cfg.max_request_points < 2 ||
+      cfg.max_request_points > (int64_t(1) << 24) || cfg.max_request_periods < 1 ||
+      cfg.max_request_periods > INT32_MAX || cfg.tick_cost < 0.0)
+    return srv_error(nullptr, BLS_ERR_INVALID_ARG, "bad server configuration");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0)
+    return srv_error(nullptr, BLS_ERR_DEVICE, "no HIP device available");
+  if (cfg.device < 0 || cfg.device >= ndev)
+    return srv_error(nullptr, BLS_ERR_INVALID_ARG, "device ordinal out of range");
+
+  bls_server *s = new (std::nothrow) bls_server();
+  if (!s) return srv_error(nullptr, BLS_ERR_NO_MEMORY, "host allocation");
+  s->cfg = cfg;
+  s->device = cfg.device;
+  s->t0 = s->t_reset = std::chrono::steady_clock::now();
+  auto fail = [&](int st) {
+    g_server_create_error = s->last_error;
+    bls_server_destroy(s);
+    return st;
+  };
+  if ((e = hipSetDevice(s->device))) return fail(srv_hip(s, e, "set device"));
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, s->device))) return fail(srv_hip(s, e, "properties"));
+  s->num_cus = prop.multiProcessorCount;
+  s->max_lds = (int)prop.sharedMemPerBlock;
+  if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) ||
+      (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)))
+    return fail(srv_hip(s, e, "create streams"));
+
+  // Arena: point arrays (t, x, w, dt: 8 B; q, qw: 4 B) and period arrays
+  // (periods 8 B; sr, depth, jstart, kwidth 4 B) in a fixed ratio.
+  const int64_t per_unit = 40 + 24 * kPeriodsPerPoint;
+  s->cap_pts = cfg.arena_bytes / per_unit;
+  s->cap_per = s->cap_pts * kPeriodsPerPoint;
+  const size_t P = (size_t)s->cap_pts, Q = (size_t)s->cap_per, M = (size_t)cfg.max_slots;
+  struct {
+    void **ptr;
+    size_t bytes;
+  } req[] = {{(void **)&s->d_t, 8 * P},        {(void **)&s->d_x, 8 * P},
+             {(void **)&s->d_w, 8 * P},        {(void **)&s->d_dt, 8 * P},
+             {(void **)&s->d_q, 4 * P},        {(void **)&s->d_qw, 4 * P},
+             {(void **)&s->d_per, 8 * Q},      {(void **)&s->d_sr, 4 * Q},
+             {(void **)&s->d_depth, 4 * Q},    {(void **)&s->d_js, 4 * Q},
+             {(void **)&s->d_ks, 4 * Q},       {(void **)&s->d_curves, sizeof(CurveDesc) * M},
+             {(void **)&s->d_keys, 8 * M}};
+  for (auto &r : req)
+    if ((e = device_alloc(r.ptr, r.bytes))) return fail(srv_hip(s, e, "allocate arena"));
+  for (int b = 0; b < kTickBuffers; ++b) {
+    if ((e = device_alloc((void **)&s->d_seg_start[b], 8 * (M + 1))) ||
+        (e = device_alloc((void **)&s->d_seg_curve[b], 4 * M)) ||
+        (e = device_alloc((void **)&s->d_seg_tile0[b], 4 * M)) ||
+        (e = device_alloc((void **)&s->d_counter[b], 64)))
+      return fail(srv_hip(s, e, "allocate tick buffers"));
+    if ((e = hipHostMalloc((void **)&s->h_seg_start[b], 8 * (M + 1), 0)) ||
+        (e = hipHostMalloc((void **)&s->h_seg_curve[b], 4 * M, 0)) ||
+        (e = hipHostMalloc((void **)&s->h_seg_tile0[b], 4 * M, 0)))
+      return fail(srv_hip(s, e, "allocate pinned tick buffers"));
+    if ((e = hipEventCreate(&s->ev_s[b])) || (e = hipEventCreate(&s->ev_e[b])))
+      return fail(srv_hip(s, e, "create events"));
+  }
+  if ((e = hipHostMalloc((void **)&s->h_curves, sizeof(CurveDesc) * M, 0)))
+    return fail(srv_hip(s, e, "allocate pinned descriptors"));
+  s->pts_arena.reset(P, kArenaAlign);
+  s->per_arena.reset(Q, kArenaAlign);
+  s->slots.assign(M, nullptr);
+  s->lds_budget = default_tiles(false).lds_budget;
+  // about 40 launches' worth of work per second at full rate keeps launch
+  // overhead negligible while new requests wait at most a few milliseconds
+  s->tick_cost = cfg.tick_cost > 0.0 ? cfg.tick_cost : 4.0e9;
+  s->thr = std::thread(scheduler, s);
+  *out = s;
+  return BLS_OK;
+}
+
+int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
+  if (!s) return BLS_ERR_INVALID_ARG;
+  if (!q || !ticket) return srv_error(s, BLS_ERR_INVALID_ARG, "request and ticket are required");
+  if (q->n > s->cfg.max_request_points || q->nperiods > s->cfg.max_request_periods) {
+    std::lock_guard<std::mutex> g(s->mu);
+    return srv_error(s, BLS_ERR_CAPACITY, "request exceeds max_request_points/periods");
+  }
+  if (q->nbins > s->cfg.max_nbins) {
+    std::lock_guard<std::mutex> g(s->mu);
+    return srv_error(s, BLS_ERR_CAPACITY, "nbins exceeds max_nbins");
+  }
+  // Same checks as the single-curve search, on the host.
+  int64_t n_off[2] = {0, q->n};
+  bls_batch b;
+  memset(&b, 0, sizeof b);
+  b.ncurves = 1;
+  b.n_off = n_off;
+  b.times = q->times;
+  b.flux = q->flux;
+  b.weights = q->weights;
+  b.periods = q->periods;
+  b.nperiods_shared = q->nperiods;
+  b.nbins_all = q->nbins;
+  b.qmin_all = q->qmin;
+  b.qmax_all = q->qmax;
+  bls_plan_config pc;
+  bls_plan_config_init(&pc);
+  pc.max_points = q->n > 2 ? q->n : 2;
+  pc.max_periods = q->nperiods > 1 ? q->nperiods : 1;
+  pc.max_nbins = s->cfg.max_nbins;
+  std::vector<CurveShape> shapes;
+  std::string err;
+  int st = q->n < 2 ? BLS_ERR_INVALID_ARG : validate_batch(pc, b, true, shapes, err);
+  if (st != BLS_OK) {
+    std::lock_guard<std::mutex> g(s->mu);
+    return srv_error(s, st, q->n < 2 ? "need n >= 2" : err);
+  }
+  const CurveShape &cs = shapes[0];
+  auto r = std::make_unique<Req>();
+  r->n = q->n;
+  r->np = q->nperiods;
+  r->nbins = cs.nbins;
+  r->kmin = cs.kmin;
+  r->kmax = cs.kmax;
+  r->weighted = q->weights != nullptr;
+  r->t.assign(q->times, q->times + q->n);
+  r->x.assign(q->flux, q->flux + q->n);
+  if (r->weighted) r->w.assign(q->weights, q->weights + q->n);
+  r->per.assign(q->periods, q->periods + q->nperiods);
+  const int wpb = r->weighted ? 2 : 1;
+  const int per_period = (r->nbins + std::max(r->kmax - 1, 1)) * 8 * wpb;
+  int T = std::max(1, s->lds_budget / per_period);
+  T = std::min<int64_t>(std::min(T, kTileMax), r->np);
+  r->tile = T;
+  r->ntiles = (int32_t)((r->np + T - 1) / T);
+  const double nw = (double)(r->kmax - r->kmin + 1);
+  r->item_cost = (double)T * ((double)r->n + 1.6 * (double)r->nbins * nw);
+  r->pp = (double)r->n * (double)r->np;
+  r->evals = (double)r->nbins * nw * (double)r->np;
+
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->device_error) return srv_error(s, BLS_ERR_DEVICE, "server stopped after a device error");
+  if (!s->pts_arena.fits_ever((size_t)r->n) || !s->per_arena.fits_ever((size_t)r->np) ||
+      per_period > s->max_lds - 1024)
+    return srv_error(s, BLS_ERR_CAPACITY, "request larger than the server's device arena");
+  r->ticket = s->next_ticket++;
+  r->submit_s = now_s(s);
+  *ticket = r->ticket;
+  s->pending.push_back(r.get());
+  s->reqs[r->ticket] = std::move(r);
+  s->submitted++;
+  s->cv_work.notify_one();
+  return BLS_OK;
+}
+
+static void fill_result(const Req *r, bls_result *out) {
+  memset(out, 0, sizeof *out);
+  out->status = r->status;
+  out->nperiods = r->status == BLS_OK ? r->np : 0;
+  out->sr = r->sr.data();
+  out->depth = r->depth.data();
+  out->jstart = r->js.data();
+  out->kwidth = r->ks.data();
+  out->best_index = r->best;
+  out->submit_s = r->submit_s;
+  out->admit_s = r->admit_s;
+  out->done_s = r->done_s;
+}
+
+int bls_server_poll(bls_server *s, uint64_t ticket, bls_result *out) {
+  if (!s || !out) return BLS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return srv_error(s, BLS_ERR_INVALID_ARG, "unknown ticket");
+  if (!it->second->finished) return BLS_ERR_BUSY;
+  fill_result(it->second.get(), out);
+  return BLS_OK;
+}
+
+int bls_server_wait(bls_server *s, uint64_t ticket, bls_result *out, double timeout_s) {
+  if (!s || !out) return BLS_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return srv_error(s, BLS_ERR_INVALID_ARG, "unknown ticket");
+  Req *r = it->second.get();
+  const auto deadline =
+      std::chrono::steady_clock::now() + std::chrono::duration<double>(std::max(0.0, timeout_s));
+  while (!r->finished) {
+    if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && !r->finished)
+      return BLS_ERR_TIMEOUT;
+  }
+  fill_result(r, out);
+  return BLS_OK;
+}
+
+int bls_server_release(bls_server *s, uint64_t ticket) {
+  if (!s) return BLS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end() || !it->second->finished)
+    return srv_error(s, BLS_ERR_INVALID_ARG, "unknown or unfinished ticket");
+  s->reqs.erase(it);
+  return BLS_OK;
+}
+
+int bls_server_get_stats(bls_server *s, bls_server_stats *out) {
+  if (!s || !out) return BLS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  memset(out, 0, sizeof *out);
+  out->submitted = s->submitted;
+  out->admitted = s->admitted;
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->queued = (int64_t)s->pending.size();
+  int64_t active = 0;
+  for (Req *r : s->slots) active += r != nullptr;
+  out->active = active;
+  out->ticks = s->ticks;
+  out->p50_ms = s->lat.percentile(50.0);
+  out->p99_ms = s->lat.percentile(99.0);
+  out->mean_ms = s->lat.mean();
+  out->max_ms = s->lat.max();
+  out->trial_points = s->pp_done;
+  out->box_evals = s->evals_done;
+  out->busy_s = s->busy_s;
+  out->wall_s =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t_reset).count();
+  out->device_bytes_in_use =
+      (int64_t)(s->pts_arena.in_use() * 40 + s->per_arena.in_use() * 24);
+  out->device_bytes_peak = (int64_t)(s->pts_arena.peak() * 40 + s->per_arena.peak() * 24);
+  return BLS_OK;
+}
+
+int bls_server_reset_stats(bls_server *s) {
+  if (!s) return BLS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  s->submitted = s->admitted = s->completed = s->failed = s->ticks = 0;
+  s->pp_done = s->evals_done = s->busy_s = 0.0;
+  s->lat.clear();
+  s->t_reset = std::chrono::steady_clock::now();
+  return BLS_OK;
+}
+
+int bls_server_drain(bls_server *s, double timeout_s) {
+  if (!s) return BLS_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  const auto deadline =
+      std::chrono::steady_clock::now() + std::chrono::duration<double>(std::max(0.0, timeout_s));
+  auto idle = [&] {
+    if (!s->pending.empty()) return false;
+    for (Req *r : s->slots)
+      if (r) return false;
+    return true;
+  };
+  while (!idle()) {
+    if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && !idle())
+      return BLS_ERR_TIMEOUT;
+  }
+  return s->device_error ? BLS_ERR_DEVICE : BLS_OK;
+}
+
+int bls_server_last_error(const bls_server *s, char *buf, size_t len) {
+  if (!buf || len == 0) return BLS_ERR_INVALID_ARG;
+  const std::string &m = s ? s->last_error : g_server_create_error;
+  const size_t n = std::min(len - 1, m.size());
+  memcpy(buf, m.data(), n);
+  buf[n] = '\0';
+  return BLS_OK;
+}
+
+int bls_server_destroy(bls_server *s) {
+  if (!s) return BLS_OK;
+  if (s->thr.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      s->stop = true;
+    }
+    s->cv_work.notify_all();
+    s->thr.join();
+  }
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+  for (void *d : {(void *)s->d_t, (void *)s->d_x, (void *)s->d_w, (void *)s->d_dt,
+                  (void *)s->d_q, (void *)s->d_qw, (void *)s->d_per, (void *)s->d_sr,
+                  (void *)s->d_depth, (void *)s->d_js, (void *)s->d_ks, (void *)s->d_curves,
+                  (void *)s->d_keys})
+    if (d) (void)hipFree(d);
+  for (int b = 0; b < kTickBuffers; ++b) {
+    for (void *d : {(void *)s->d_seg_start[b], (void *)s->d_seg_curve[b],
+                    (void *)s->d_seg_tile0[b], (void *)s->d_counter[b]})
+      if (d) (void)hipFree(d);
+    for (void *h : {(void *)s->h_seg_start[b], (void *)s->h_seg_curve[b],
+                    (void *)s->h_seg_tile0[b]})
+      if (h) (void)hipHostFree(h);
+    if (s->ev_s[b]) (void)hipEventDestroy(s->ev_s[b]);
+    if (s->ev_e[b]) (void)hipEventDestroy(s->ev_e[b]);
+  }
+  if (s->h_curves) (void)hipHostFree(s->h_curves);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  delete s;
+  return BLS_OK;
+}
+
+}  // extern "C"

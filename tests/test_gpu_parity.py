@@ -251,3 +251,46 @@ def test_host_errors_leave_outputs_untouched(bls, plan):
     assert ei.value.status == bls.BLS_ERR_CAPACITY
     # the plan is still usable
     check_curve(lc, _run(bls, plan, lc), _orc(lc), label="after errors")
+
+
+@pytest.mark.parametrize("cadence", ["nightly", "minute_grid"])
+def test_phase_bins_bit_exact(bls, plan, cadence):
+    """Where FP64 rounding decides an integer (the bin), both sides decide in
+    FP64 with the same operation order: bins must be identical."""
+    rng = np.random.default_rng(12)
+    if cadence == "nightly":
+        t = synth.nightly_times(rng, 20000, nights=60)
+    else:
+        t = synth.minute_grid_times(50000)
+    periods = np.concatenate([
+        synth.log_period_grid(0.1, 20.0, 40), [1.0, 0.5, 1.0 / 3.0, 2.0,
+                                               1.0 / 1440.0 * 97]])
+    _say("bins", cadence, t.size)
+    for P in periods:
+        for nbins in (200, 1000, 4096):
+            g = bls.bls_debug_phase_bins(plan, t, P, nbins)
+            o, *_ = oracle.bins(t, np.ones_like(t), None, P, nbins)
+            assert np.array_equal(g, o), (cadence, P, nbins,
+                                          int(np.sum(g != o)))
+
+
+def test_device_api_reports_bad_period(bls):
+    import torch
+    b = synth.uniform_batch(2, 300, 50, 100, seed=80)
+    per = b.periods.copy()
+    per[7] = -1.0
+    dev = torch.device("cuda:0")
+    _say("device bad period")
+    m = per.size * 2
+    with bls.Plan(max_curves=4, max_points=4096, max_periods=4096) as p:
+        args = [torch.tensor(a, device=dev) for a in (b.t, b.x, per)]
+        outs = [torch.empty(m, device=dev, dtype=torch.float32),
+                torch.empty(m, device=dev, dtype=torch.float32),
+                torch.empty(m, device=dev, dtype=torch.int32),
+                torch.empty(m, device=dev, dtype=torch.int32),
+                torch.empty(2, device=dev, dtype=torch.int64)]
+        bls.bls_search_device(p.handle, b.n_off, args[0], args[1], None,
+                              args[2], None, 100, 0.01, 0.1, *outs)
+        with pytest.raises(bls.BlsError) as ei:
+            bls.bls_synchronize(p.handle)
+        assert "trial period" in str(ei.value)
