@@ -248,6 +248,10 @@ __device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
 }
 
 // Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
+// Each thread takes kPPT consecutive points, so the 64 lanes of one atomic
+// instruction hold points kPPT apart in time: their phases (hence bins and
+// LDS banks) are far less correlated than those of 64 consecutive points of
+// a sorted light curve, which cuts same-bin and same-bank collisions.
 // Each period's histogram has nb + 1 words: the extra word catches the
 // clamp case and is added to bin nb - 1 when the histogram is decoded.
 template <bool WEIGHTED, bool FULL>
@@ -265,7 +269,7 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   bool ok[kPPT];
 #pragma unroll
   for (int r = 0; r < kPPT; ++r) {
-    const int64_t i = base + (int64_t)r * kBlock + tid;
+    const int64_t i = base + (int64_t)tid * kPPT + r;
     ok[r] = FULL || i < n;
     d[r] = 0.0;
     va[r] = 0;
