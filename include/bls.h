@@ -200,6 +200,66 @@ int bls_last_error(const bls_plan *plan, char *buf, size_t len);
 const char *bls_status_string(int status);
 
 /*
+ * Detection statistics of each curve's periodogram (the step after the
+ * search: the signal detection efficiency of the cited BLS statistic and
+ * the strongest peaks).  Per curve, over its m trial periods:
+ *   mean_sr, std_sr: mean and population standard deviation of SR;
+ *   sde = (max SR - mean_sr) / std_sr (0 if std_sr is 0);
+ *   peaks: up to max_peaks (<= BLS_MAX_PEAKS), each the largest SR among
+ *   periods not yet suppressed (ties: smallest index); a peak at P suppresses
+ *   every period P' with |P' - h P| <= window * h P, h in {1, 1/2, 2, 1/3, 3};
+ *   the search stops when no unsuppressed period has SR > 0;
+ *   peak_sde = (peak SR - mean_sr) / std_sr; candidate = sde >= sde_threshold.
+ * batch: as for bls_search_device (periods are device pointers); sr: device
+ * [results] as written by bls_search_device for that batch.  out: host
+ * [ncurves].  Synchronous on the plan's stream.  Errors: INVALID_ARG,
+ * CAPACITY (a curve with more than 2^20 periods), DEVICE.
+ */
+#define BLS_MAX_PEAKS 16
+typedef struct {
+    double mean_sr;
+    double std_sr;
+    double sde;
+    int32_t npeaks;
+    int32_t candidate;
+    int64_t peak_index[BLS_MAX_PEAKS];
+    float peak_sr[BLS_MAX_PEAKS];
+    float peak_sde[BLS_MAX_PEAKS];
+} bls_detection;
+
+int bls_detect_device(bls_plan *plan, const bls_batch *batch, const float *sr,
+                      int32_t max_peaks, double window, double sde_threshold,
+                      bls_detection *out);
+
+/*
+ * Eclipse detection efficiency of observing cadences: the chance that at
+ * least min_eclipses eclipses of a binary with a given period fall on
+ * observations, given the real cadence with its daytime and weather gaps
+ * (the simulation behind the paper's detection-efficiency figure, section
+ * 3).  Per cadence and trial period P (f = 1/P):
+ *   the kept times (weight > 0; all if weights is NULL) are folded into
+ *   nphase phase bins as in the search (t0 = min kept time, bin =
+ *   min(trunc(frac((t - t0) f) nphase), nphase - 1), FP64);
+ *   the eclipse of trial epoch j (0 <= j < nphase) covers bins j .. j+k-1
+ *   modulo nphase, k = lround(duration f nphase) clamped to [1, nphase];
+ *   a point of cycle floor((t - t0) f) in bin b lies in that cycle's eclipse
+ *   when b >= j and in the previous cycle's when the window wrapped (b < j);
+ *   observed[r] = number of epochs j with at least min_eclipses distinct
+ *   eclipses holding a kept point; the efficiency is observed[r] / nphase.
+ * cadences: a bls_batch whose times, weights and periods are DEVICE pointers
+ * (flux, nbins, qmin, qmax are ignored); each cadence needs >= 1 point.
+ * observed: DEVICE int32 [results], indexed as bls_search_device's results.
+ * nphase <= BLS_MAX_NBINS; duration > 0 in the units of the times;
+ * min_eclipses 1 or 2.  Synchronous on the plan's stream.  Errors:
+ * INVALID_ARG (bad arguments; a cadence with a non-finite kept time, a bad
+ * weight, no kept point or a bad period: its results are -1), CAPACITY
+ * (plan limits, or more than 2^29 cycles in one cadence), DEVICE.
+ */
+int bls_eclipse_window_device(bls_plan *plan, const bls_batch *cadences,
+                              int32_t nphase, double duration,
+                              int32_t min_eclipses, int32_t *observed);
+
+/*
  * Diagnostic: the phase bin the search kernel assigns to each point of one
  * curve (unit weights) at one trial period, computed by the same device
  * code (t0 = min time, d = t - t0, f = 1/P, bin = min(trunc(frac(d f)

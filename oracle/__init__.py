@@ -59,6 +59,19 @@ def _load():
     lib.bls_oracle_bins.argtypes = [
         P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P, P, P, P]
     lib.bls_oracle_bins.restype = ctypes.c_int64
+    lib.bls_oracle_detect.argtypes = [
+        P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+        ctypes.c_double, P, P, P, P, P, P, P, P]
+    lib.bls_oracle_detect.restype = ctypes.c_int
+    lib.bls_oracle_eclipse_window.argtypes = [
+        P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32,
+        ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P]
+    lib.bls_oracle_eclipse_window.restype = ctypes.c_int
+    lib.bls_oracle_variability.argtypes = [
+        P, P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+        ctypes.c_double, ctypes.c_int32, P, P, P, P, P, P]
+    lib.bls_oracle_variability.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -148,3 +161,87 @@ def bins(t, x, w, period, nbins):
     if m < 0:
         raise OracleError("oracle rejected the input (status %d)" % m)
     return b[:m], hw, hs, hn
+
+
+def detect(sr, periods, max_peaks=8, window=0.01, threshold=7.0):
+    """Detection statistics of one periodogram (see bls_oracle.h)."""
+    lib = _load()
+    sr = _f64(sr)
+    periods = _f64(periods)
+    m = sr.shape[0]
+    mean, std, sde = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    pi = np.full(max(max_peaks, 1), -1, np.int64)
+    ps = np.zeros(max(max_peaks, 1))
+    pd = np.zeros(max(max_peaks, 1))
+    npk, cand = ctypes.c_int32(), ctypes.c_int32()
+    st = lib.bls_oracle_detect(_ptr(sr), _ptr(periods), m, int(max_peaks),
+                               float(window), float(threshold),
+                               ctypes.byref(mean), ctypes.byref(std),
+                               ctypes.byref(sde), _ptr(pi), _ptr(ps),
+                               _ptr(pd), ctypes.byref(npk),
+                               ctypes.byref(cand))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    k = npk.value
+    return dict(mean=mean.value, std=std.value, sde=sde.value,
+                peak_index=pi[:k], peak_sr=ps[:k], peak_sde=pd[:k],
+                candidate=bool(cand.value))
+
+
+def eclipse_window(t, w, periods, nphase, duration, min_eclipses=2,
+                   nthreads=0):
+    """Observed-epoch counts of the eclipse detection efficiency.
+
+    Returns int32 [nperiods]: for each period, how many of the nphase trial
+    eclipse epochs give at least min_eclipses distinct eclipses that fall on
+    kept observations (readings W1-W4 in bls_oracle.c); divide by nphase for
+    the efficiency.
+    """
+    lib = _load()
+    t = _f64(t)
+    w = None if w is None else _f64(w)
+    periods = _f64(periods)
+    if w is not None and w.shape[0] != t.shape[0]:
+        raise OracleError("length mismatch")
+    out = np.empty(periods.shape[0], np.int32)
+    st = lib.bls_oracle_eclipse_window(
+        _ptr(t), _ptr(w), t.shape[0], _ptr(periods), periods.shape[0],
+        int(nphase), float(duration), int(min_eclipses), int(nthreads),
+        _ptr(out))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    return out
+
+
+def variability(x, w, n_off, mag, chip_off, nmagbins, origin=0.0, width=0.1,
+                clip_sigma=3.0, max_iter=5, flag_sigma=2.0, min_stars=3):
+    """High-variability pre-search (readings V1-V4 in bls_oracle.c).
+
+    Returns a dict: rms, bin, flag per star; mean, std, count per
+    (chip, magnitude bin), shaped [nchips, nmagbins].
+    """
+    lib = _load()
+    x = _f64(x)
+    w = None if w is None else _f64(w)
+    n_off = np.ascontiguousarray(n_off, np.int64)
+    chip_off = np.ascontiguousarray(chip_off, np.int64)
+    mag = _f64(mag)
+    nc = n_off.shape[0] - 1
+    nk = chip_off.shape[0] - 1
+    if mag.shape[0] != nc or n_off[-1] != x.shape[0]:
+        raise OracleError("length mismatch")
+    rms = np.empty(nc)
+    b = np.empty(nc, np.int32)
+    f = np.empty(nc, np.int32)
+    bm = np.empty(nk * nmagbins)
+    bs = np.empty(nk * nmagbins)
+    bc = np.empty(nk * nmagbins, np.int32)
+    st = lib.bls_oracle_variability(
+        _ptr(x), _ptr(w), _ptr(n_off), nc, _ptr(mag), _ptr(chip_off), nk,
+        float(origin), float(width), int(nmagbins), float(clip_sigma),
+        int(max_iter), float(flag_sigma), int(min_stars), _ptr(rms), _ptr(b),
+        _ptr(f), _ptr(bm), _ptr(bs), _ptr(bc))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    return dict(rms=rms, bin=b, flag=f, mean=bm.reshape(nk, nmagbins),
+                std=bs.reshape(nk, nmagbins), count=bc.reshape(nk, nmagbins))

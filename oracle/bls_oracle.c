@@ -368,3 +368,332 @@ int64_t bls_oracle_bins(const double *t, const double *x, const double *w,
     free_kept(&kc);
     return m;
 }
+
+/*
+ * Detection statistics (signal detection efficiency of the cited BLS
+ * statistic, plus alias-suppressed peaks); see bls_oracle.h for the rules.
+ * Reading: the window is relative to the peak period, and the harmonic set
+ * is fixed at 1/3, 1/2, 1, 2, 3.
+ */
+int bls_oracle_detect(const double *sr, const double *periods, int64_t m,
+                      int32_t max_peaks, double window, double threshold,
+                      double *mean, double *std, double *sde,
+                      int64_t *peak_index, double *peak_sr, double *peak_sde,
+                      int32_t *npeaks, int32_t *candidate)
+{
+    static const double harmonics[5] = {1.0, 0.5, 2.0, 1.0 / 3.0, 3.0};
+    if (m < 1 || !sr || !periods || max_peaks < 0 || !(window >= 0.0))
+        return BLS_ORACLE_INVALID;
+
+    double sum = 0.0;
+    for (int64_t p = 0; p < m; ++p)
+        sum = sum + sr[p];
+    double mu = sum / (double)m;
+    double ss = 0.0;
+    for (int64_t p = 0; p < m; ++p)
+        ss = ss + (sr[p] - mu) * (sr[p] - mu);
+    double sd = sqrt(ss / (double)m);
+    double best = sr[0];
+    for (int64_t p = 1; p < m; ++p)
+        if (sr[p] > best)
+            best = sr[p];
+    double s = sd > 0.0 ? (best - mu) / sd : 0.0;
+
+    unsigned char *off = (unsigned char *)calloc((size_t)m, 1);
+    if (!off)
+        return BLS_ORACLE_NOMEM;
+    int32_t k = 0;
+    while (k < max_peaks) {
+        int64_t pk = -1;
+        for (int64_t p = 0; p < m; ++p)
+            if (!off[p] && sr[p] > 0.0 && (pk < 0 || sr[p] > sr[pk]))
+                pk = p;
+        if (pk < 0)
+            break;
+        peak_index[k] = pk;
+        peak_sr[k] = sr[pk];
+        peak_sde[k] = sd > 0.0 ? (sr[pk] - mu) / sd : 0.0;
+        ++k;
+        for (int64_t p = 0; p < m; ++p) {
+            for (int h = 0; h < 5; ++h) {
+                double c = harmonics[h] * periods[pk];
+                if (fabs(periods[p] - c) <= window * c) {
+                    off[p] = 1;
+                    break;
+                }
+            }
+        }
+    }
+    free(off);
+    *mean = mu;
+    *std = sd;
+    *sde = s;
+    *npeaks = k;
+    *candidate = s >= threshold ? 1 : 0;
+    return BLS_ORACLE_OK;
+}
+
+/*
+ * Eclipse detection efficiency of an observing cadence (the simulation
+ * behind the paper's detection-efficiency figure, section 3: the chance that
+ * at least two eclipses of a binary of given period fall on observations,
+ * given the real cadence with its daytime and weather gaps).  Readings:
+ *   W1  only the times matter; points with weight 0 are not observations
+ *       (a NULL weight array keeps every point); t0 = min kept time;
+ *   W2  eclipse epochs are a grid of nphase phase offsets j / nphase; the
+ *       eclipse starting at offset j covers the k phase bins j .. j+k-1
+ *       (modulo nphase) of the fold of reading R3 with nphase bins, where
+ *       k = lround(duration * f * nphase) clamped to [1, nphase], f = 1/P;
+ *   W3  a point of cycle E = floor(d f) in bin b lies in eclipse event E when
+ *       b >= j and in event E - 1 when the window wrapped past the end of the
+ *       cycle (b < j); an event is observed when at least one point lies in
+ *       it;
+ *   W4  observed[p] = number of offsets j with at least min_eclipses
+ *       distinct observed events; the efficiency is observed[p] / nphase.
+ * Events are counted here by sorting the event numbers of the in-eclipse
+ * points of each offset; nothing is shared across offsets.
+ */
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+int bls_oracle_eclipse_window(const double *t, const double *w, int64_t n,
+                              const double *periods, int64_t nperiods,
+                              int32_t nphase, double duration,
+                              int32_t min_eclipses, int32_t nthreads,
+                              int32_t *observed)
+{
+    if (!t || !periods || !observed || n < 1 || nperiods < 1 || nphase < 1 ||
+        !(duration > 0.0) || !isfinite(duration) || min_eclipses < 1)
+        return BLS_ORACLE_INVALID;
+    for (int64_t p = 0; p < nperiods; ++p)
+        if (!isfinite(periods[p]) || !(periods[p] > 0.0))
+            return BLS_ORACLE_INVALID;
+    int64_t m = 0;
+    double t0 = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double wi = w ? w[i] : 1.0;
+        if (!isfinite(wi) || wi < 0.0)
+            return BLS_ORACLE_INVALID;
+        if (wi == 0.0)
+            continue;
+        if (!isfinite(t[i]))
+            return BLS_ORACLE_INVALID;
+        if (t[i] < t0)
+            t0 = t[i];
+        ++m;
+    }
+    if (m < 1)
+        return BLS_ORACLE_INVALID;
+    double *d = (double *)malloc((size_t)m * sizeof(double));
+    if (!d)
+        return BLS_ORACLE_NOMEM;
+    for (int64_t i = 0, k = 0; i < n; ++i)
+        if (!w || w[i] != 0.0)
+            d[k++] = t[i] - t0;
+
+    int fail = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel reduction(| : fail)
+#endif
+    {
+        int32_t *bin = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        int64_t *cyc = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+        int64_t *ev = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+        if (!bin || !cyc || !ev)
+            fail = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+        for (int64_t p = 0; p < nperiods; ++p) {
+            if (fail)
+                continue;
+            double f = 1.0 / periods[p];
+            long kw = lround(duration * f * (double)nphase);
+            if (kw < 1)
+                kw = 1;
+            if (kw > nphase)
+                kw = nphase;
+            for (int64_t i = 0; i < m; ++i) {
+                double c = d[i] * f;
+                double e = floor(c);
+                cyc[i] = (int64_t)e;
+                bin[i] = phase_bin(d[i], f, nphase);
+            }
+            int32_t count = 0;
+            for (int32_t j = 0; j < nphase; ++j) {
+                int64_t ne = 0;
+                for (int64_t i = 0; i < m; ++i) {
+                    int32_t off = bin[i] - j;
+                    if (off < 0)
+                        off += nphase;
+                    if (off < kw)
+                        ev[ne++] = bin[i] >= j ? cyc[i] : cyc[i] - 1;
+                }
+                qsort(ev, (size_t)ne, sizeof(int64_t), cmp_i64);
+                int64_t distinct = 0;
+                for (int64_t q = 0; q < ne; ++q)
+                    if (q == 0 || ev[q] != ev[q - 1])
+                        ++distinct;
+                if (distinct >= min_eclipses)
+                    ++count;
+            }
+            observed[p] = count;
+        }
+        free(bin);
+        free(cyc);
+        free(ev);
+    }
+    free(d);
+    return fail ? BLS_ORACLE_NOMEM : BLS_ORACLE_OK;
+}
+
+/*
+ * High-variability pre-search (section 2.2.1, "High-variability source
+ * searches"): the photometric stability expected at a star's magnitude is
+ * a sigma-clipped average over the stars of the same chip in 0.1-mag bins;
+ * stars more variable than that by more than 2 sigma are flagged.
+ * Readings:
+ *   V1  a star's stability is the population RMS about the mean of its kept
+ *       values (weight > 0, NULL weights keep all), unweighted, in the
+ *       values' own units; a star with no kept value, or a non-finite kept
+ *       value or bad weight, is invalid (flag -1, in no bin);
+ *   V2  its magnitude bin is floor((mag - origin) / width); stars whose bin
+ *       falls outside [0, nmagbins), or whose magnitude is not finite, are in
+ *       no bin (flag 0);
+ *   V3  per (chip, bin) the clipped set starts as all member stars, in star
+ *       order; a round takes the mean and population deviation of the set
+ *       and drops every member farther than clip_sigma deviations from the
+ *       mean (inclusive bounds keep a member exactly at the limit); rounds
+ *       repeat until one drops nothing or max_iter rounds have dropped
+ *       something; the bin's mean and deviation are those of the final set;
+ *   V4  a member star is flagged when its stability exceeds the bin mean by
+ *       more than flag_sigma deviations and the final set holds at least
+ *       min_stars stars.
+ */
+static void mean_std(const double *v, int64_t n, double *mu, double *sd)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s = s + v[i];
+    double m = s / (double)n;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        ss = ss + (v[i] - m) * (v[i] - m);
+    *mu = m;
+    *sd = sqrt(ss / (double)n);
+}
+
+int bls_oracle_variability(const double *x, const double *w,
+                           const int64_t *n_off, int64_t ncurves,
+                           const double *mag, const int64_t *chip_off,
+                           int64_t nchips, double origin, double width,
+                           int32_t nmagbins, double clip_sigma,
+                           int32_t max_iter, double flag_sigma,
+                           int32_t min_stars, double *rms, int32_t *bin,
+                           int32_t *flag, double *bin_mean, double *bin_std,
+                           int32_t *bin_count)
+{
+    if (!x || !n_off || !mag || !chip_off || ncurves < 1 || nchips < 1 ||
+        nmagbins < 1 || !(width > 0.0) || !isfinite(origin) ||
+        !isfinite(width) || !(clip_sigma > 0.0) || max_iter < 0 ||
+        !(flag_sigma >= 0.0) || min_stars < 1 || n_off[0] != 0 ||
+        chip_off[0] != 0 || chip_off[nchips] != ncurves)
+        return BLS_ORACLE_INVALID;
+
+    /* V1, V2: per star */
+    for (int64_t c = 0; c < ncurves; ++c) {
+        int64_t a = n_off[c], b = n_off[c + 1];
+        int64_t m = 0;
+        int bad = 0;
+        double s = 0.0;
+        for (int64_t i = a; i < b; ++i) {
+            double wi = w ? w[i] : 1.0;
+            if (!isfinite(wi) || wi < 0.0) {
+                bad = 1;
+                continue;
+            }
+            if (wi == 0.0)
+                continue;
+            if (!isfinite(x[i]))
+                bad = 1;
+            s = s + x[i];
+            ++m;
+        }
+        flag[c] = 0;
+        bin[c] = -1;
+        if (bad || m == 0) {
+            rms[c] = NAN;
+            flag[c] = -1;
+            continue;
+        }
+        double mu = s / (double)m;
+        double ss = 0.0;
+        for (int64_t i = a; i < b; ++i) {
+            double wi = w ? w[i] : 1.0;
+            if (wi == 0.0)
+                continue;
+            ss = ss + (x[i] - mu) * (x[i] - mu);
+        }
+        rms[c] = sqrt(ss / (double)m);
+        if (isfinite(mag[c])) {
+            double q = floor((mag[c] - origin) / width);
+            if (q >= 0.0 && q < (double)nmagbins)
+                bin[c] = (int32_t)q;
+        }
+    }
+
+    /* V3, V4: per chip and bin */
+    double *vals = (double *)malloc((size_t)ncurves * sizeof(double));
+    double *next = (double *)malloc((size_t)ncurves * sizeof(double));
+    if (!vals || !next) {
+        free(vals);
+        free(next);
+        return BLS_ORACLE_NOMEM;
+    }
+    for (int64_t k = 0; k < nchips; ++k) {
+        for (int32_t b = 0; b < nmagbins; ++b) {
+            int64_t cnt = 0;
+            for (int64_t c = chip_off[k]; c < chip_off[k + 1]; ++c)
+                if (bin[c] == b && flag[c] >= 0)
+                    vals[cnt++] = rms[c];
+            int64_t slot = k * nmagbins + b;
+            if (cnt == 0) {
+                bin_mean[slot] = NAN;
+                bin_std[slot] = NAN;
+                bin_count[slot] = 0;
+                continue;
+            }
+            double mu, sd;
+            mean_std(vals, cnt, &mu, &sd);
+            for (int32_t it = 0; it < max_iter; ++it) {
+                int64_t kept = 0;
+                for (int64_t i = 0; i < cnt; ++i)
+                    if (vals[i] >= mu - clip_sigma * sd &&
+                        vals[i] <= mu + clip_sigma * sd)
+                        next[kept++] = vals[i];
+                if (kept == cnt)
+                    break;
+                memcpy(vals, next, (size_t)kept * sizeof(double));
+                cnt = kept;
+                mean_std(vals, cnt, &mu, &sd);
+            }
+            bin_mean[slot] = mu;
+            bin_std[slot] = sd;
+            bin_count[slot] = (int32_t)cnt;
+            if (cnt < min_stars)
+                continue;
+            for (int64_t c = chip_off[k]; c < chip_off[k + 1]; ++c)
+                if (bin[c] == b && flag[c] >= 0 &&
+                    rms[c] > mu + flag_sigma * sd)
+                    flag[c] = 1;
+        }
+    }
+    free(vals);
+    free(next);
+    return BLS_ORACLE_OK;
+}

@@ -73,6 +73,58 @@ int64_t bls_oracle_bins(const double *t, const double *x, const double *w,
                         int64_t n, double period, int32_t nbins,
                         int32_t *bins, double *hw, double *hs, int64_t *hn);
 
+/*
+ * Detection statistics of one periodogram (the step after the search).
+ *   sr, periods: [m]; the statistic is the signal detection efficiency of the
+ *   BLS method the paper cites: SDE = (SR_max - mean SR) / std SR, with the
+ *   mean and the population standard deviation over the m periods (SDE = 0
+ *   when the deviation is 0).
+ *   Peaks: up to max_peaks, each the largest SR among periods not yet
+ *   suppressed (ties: smallest index); a peak at P* suppresses every period P
+ *   with |P - h P*| <= window * h P* for h in {1, 1/2, 2, 1/3, 3}; the search
+ *   stops early when no unsuppressed period has SR > 0.
+ * Outputs: mean, std, sde; peak_index/peak_sr/peak_sde [max_peaks]; npeaks;
+ * candidate = (sde >= threshold).
+ */
+int bls_oracle_detect(const double *sr, const double *periods, int64_t m,
+                      int32_t max_peaks, double window, double threshold,
+                      double *mean, double *std, double *sde,
+                      int64_t *peak_index, double *peak_sr, double *peak_sde,
+                      int32_t *npeaks, int32_t *candidate);
+
+/*
+ * Eclipse detection efficiency of an observing cadence (readings W1-W4 in
+ * bls_oracle.c).  t: [n] times; w: [n] weights or NULL (weight 0 = not an
+ * observation); periods: [nperiods]; nphase: trial eclipse epochs per period;
+ * duration: eclipse length in the units of t; min_eclipses >= 1.
+ * observed: [nperiods] output, the number of the nphase epochs for which at
+ * least min_eclipses distinct eclipses fall on kept observations.
+ */
+int bls_oracle_eclipse_window(const double *t, const double *w, int64_t n,
+                              const double *periods, int64_t nperiods,
+                              int32_t nphase, double duration,
+                              int32_t min_eclipses, int32_t nthreads,
+                              int32_t *observed);
+
+/*
+ * High-variability pre-search (readings V1-V4 in bls_oracle.c).
+ *   x, w: packed values and weights (w NULL = unit), n_off [ncurves + 1];
+ *   mag: [ncurves] reference magnitudes; chip_off [nchips + 1]: the stars of
+ *   chip k are [chip_off[k], chip_off[k+1]); magnitude bins of the given
+ *   width from origin, nmagbins per chip.
+ * Outputs: rms, bin, flag [ncurves]; bin_mean, bin_std, bin_count
+ * [nchips * nmagbins] (mean and deviation NaN for an empty bin).
+ */
+int bls_oracle_variability(const double *x, const double *w,
+                           const int64_t *n_off, int64_t ncurves,
+                           const double *mag, const int64_t *chip_off,
+                           int64_t nchips, double origin, double width,
+                           int32_t nmagbins, double clip_sigma,
+                           int32_t max_iter, double flag_sigma,
+                           int32_t min_stars, double *rms, int32_t *bin,
+                           int32_t *flag, double *bin_mean, double *bin_std,
+                           int32_t *bin_count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,18 @@ class BlsCallStats(C.Structure):
                 ("graph_replayed", C.c_int32)]
 
 
+BLS_MAX_PEAKS = 16
+
+
+class BlsDetection(C.Structure):
+    _fields_ = [("mean_sr", C.c_double), ("std_sr", C.c_double),
+                ("sde", C.c_double), ("npeaks", C.c_int32),
+                ("candidate", C.c_int32),
+                ("peak_index", C.c_int64 * BLS_MAX_PEAKS),
+                ("peak_sr", C.c_float * BLS_MAX_PEAKS),
+                ("peak_sde", C.c_float * BLS_MAX_PEAKS)]
+
+
 class BlsRequest(C.Structure):
     _fields_ = [("times", C.c_void_p), ("flux", C.c_void_p),
                 ("weights", C.c_void_p), ("n", C.c_int64),
@@ -139,6 +151,8 @@ def load():
         "bls_status_string": (C.c_char_p, [C.c_int]),
         "bls_last_stats": (C.c_int, [P, P]),
         "bls_debug_phase_bins": (C.c_int, [P, P, I64, D, I32, P]),
+        "bls_detect_device": (C.c_int, [P, P, P, I32, D, D, P]),
+        "bls_eclipse_window_device": (C.c_int, [P, P, I32, D, I32, P]),
     }
     optional = {
         "bls_server_config_init": (None, [P]),

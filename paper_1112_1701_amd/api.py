@@ -213,6 +213,48 @@ def bls_search_device(plan, n_off, times, flux, weights, periods, p_off,
            plan)
 
 
+def bls_detect_device(plan, n_off, periods, p_off, nbins, qmin, qmax, sr,
+                      max_peaks=8, window=0.01, sde_threshold=7.0):
+    """Detection statistics of each curve's periodogram (device SR tensor).
+
+    Returns a list of dicts (mean_sr, std_sr, sde, candidate, peak_index,
+    peak_sr, peak_sde), one per curve.
+    """
+    ba = _batch(n_off, periods, periods, None, periods, p_off, nbins, qmin,
+                qmax, device=True)
+    out = (L.BlsDetection * ba.ncurves)()
+    _check(L.load().bls_detect_device(plan, C.byref(ba.struct),
+                                      C.c_void_p(sr.data_ptr()),
+                                      int(max_peaks), float(window),
+                                      float(sde_threshold), out), plan)
+    res = []
+    for d in out:
+        k = d.npeaks
+        res.append(dict(mean_sr=d.mean_sr, std_sr=d.std_sr, sde=d.sde,
+                        candidate=bool(d.candidate),
+                        peak_index=np.array(d.peak_index[:k], np.int64),
+                        peak_sr=np.array(d.peak_sr[:k], np.float32),
+                        peak_sde=np.array(d.peak_sde[:k], np.float32)))
+    return res
+
+
+def bls_eclipse_window_device(plan, n_off, times, periods, p_off, nphase,
+                              duration, min_eclipses, observed,
+                              weights=None):
+    """Observed-epoch counts of the eclipse detection efficiency.
+
+    times, periods, weights (or None) and observed (int32) are device
+    tensors; observed receives, per cadence and period, how many of the
+    nphase trial eclipse epochs show at least min_eclipses eclipses on kept
+    observations (divide by nphase for the efficiency).  Synchronous.
+    """
+    ba = _batch(n_off, times, times, weights, periods, p_off, 2, 0.1, 0.1,
+                device=True)
+    _check(L.load().bls_eclipse_window_device(
+        plan, C.byref(ba.struct), int(nphase), float(duration),
+        int(min_eclipses), C.c_void_p(observed.data_ptr())), plan)
+
+
 class Plan:
     """Owning wrapper of a bls_plan (closes on exit)."""
 

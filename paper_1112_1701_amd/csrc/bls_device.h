@@ -87,7 +87,59 @@ struct SearchArgs {
   int32_t hist_bytes;         // dynamic LDS for histograms
 };
 
+struct DetectDesc {
+  int64_t p_off;     // first trial period of the curve
+  int64_t r_off;     // first result of the curve
+  int64_t nperiods;
+};
+
+struct DetectArgs {
+  const DetectDesc *desc;
+  const double *periods;
+  const float *sr;
+  void *out;          // bls_detection [ncurves]
+  int32_t ncurves;
+  int32_t max_peaks;
+  double window;
+  double threshold;
+  int32_t mask_words;  // LDS bitmask words (>= max nperiods / 32)
+};
+
+// Eclipse detection efficiency of an observing cadence (window function).
+struct WindowDesc {
+  int64_t n_off;        // first point of the cadence
+  int64_t n;            // its points (including zero-weight ones)
+  int64_t p_off;        // first trial period
+  int64_t r_off;        // first result slot
+  int64_t item0;        // first work item (period tile) of this cadence
+  int32_t nperiods;
+  int32_t check_periods;  // 1: the prep pass checks this cadence's periods
+  double t0;            // min kept time (written on the device)
+  int32_t status;       // CurveStatus (written on the device)
+  int32_t pad;
+};
+
+struct WindowArgs {
+  WindowDesc *desc;
+  int32_t ncurves;
+  int32_t tile;         // periods per work item
+  int64_t nitems;
+  const double *t;
+  const double *w;      // nullptr: every point is an observation
+  const double *periods;
+  int32_t *observed;
+  int32_t nphase;
+  int32_t min_eclipses; // 1 or 2
+  double duration;
+  unsigned int *overflow;  // set when a cycle number exceeds kMaxCycle
+};
+constexpr int kMaxCycle = 1 << 29;
+
+int launch_window(const WindowArgs &a, int grid, void *stream);
+int window_blocks_per_cu(int lds_bytes, int *blocks);
+
 // Launch wrappers (bls_kernels.hip).  All return hipError_t as int.
+int launch_detect(const DetectArgs &a, void *stream);
 int launch_fill(unsigned long long *counter, unsigned long long *keys,
                 int32_t nkeys,
                 void *stream);

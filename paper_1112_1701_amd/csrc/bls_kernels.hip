@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include "bls_device.h"
+#include "../../include/bls.h"
 
 namespace bls {
 namespace {
@@ -254,6 +255,9 @@ __device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
 // a sorted light curve, which cuts same-bin and same-bank collisions.
 // Each period's histogram has nb + 1 words: the extra word catches the
 // clamp case and is added to bin nb - 1 when the histogram is decoded.
+// Weighted curves use two such arrays per period, A (count, weight) then B
+// (weighted signal), each contiguous so that the lanes of one atomic spread
+// over all LDS banks.
 template <bool WEIGHTED, bool FULL>
 __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int64_t base,
                                   int np, const double *s_f, unsigned long long *s_hist,
@@ -294,10 +298,9 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
     for (int r = 0; r < kPPT; ++r) {
       if (FULL || ok[r]) {
         const int b = raw_bin(d[r], f, nbd);
-        __hip_atomic_fetch_add(h + b * wpb, va[r], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(h + b, va[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (WEIGHTED)
-          __hip_atomic_fetch_add(h + b * wpb + 1, vb[r], __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add(h + HB + b, vb[r], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
@@ -376,44 +379,78 @@ __device__ __forceinline__ void scan_task_unit(const float2 *h, int kmin, int km
 }
 
 // One lane task, weighted curves: running sums of weight R, signal S and
-// count C; screen S^2 >= theta R (W - R).
+// count C (ha: the period's (R, S) bins from start j, hc: their counts in
+// .x); screen S^2 >= theta R (W - R).
 template <bool DIP>
-__device__ __forceinline__ void scan_task_weighted(const float4 *h, int kmin, int kmax, float Wf,
-                                                   float thr, float nmax1, float mipf, float &bn,
-                                                   float &bd, int &bm) {
+__device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float2 *hc, int kmin,
+                                                   int kmax, float Wf, float thr, float nmax1,
+                                                   float mipf, float &bn, float &bd, int &bm) {
   float R = 0.0f, S = 0.0f, C = 0.0f;
   int m = 0;
   for (; m < kmin - 1; ++m) {
-    const float4 e = h[m];
+    const float2 e = ha[m];
     R += e.x;
     S += e.y;
-    C += e.z;
+    C += hc[m].x;
   }
   bn = 0.0f;
   bd = 1.0f;
   bm = -1;
-  for (; m + 2 <= kmax; m += 2) {
-    const float4 e0 = h[m], e1 = h[m + 1];
-    const float R0 = R + e0.x, S0 = S + e0.y, C0 = C + e0.z;
-    const float R1 = R0 + e1.x, S1 = S0 + e1.y, C1 = C0 + e1.z;
-    const float d0 = Wf - R0, d1 = Wf - R1;
-    const bool p0 = S0 * S0 >= thr * (R0 * d0);
-    const bool p1 = S1 * S1 >= thr * (R1 * d1);
-    if (p0 | p1) {
-      if (p0) consider<true, DIP, false>(R0, S0, C0, d0, m, nmax1, mipf, bn, bd, bm);
-      if (p1) consider<true, DIP, false>(R1, S1, C1, d1, m + 1, nmax1, mipf, bn, bd, bm);
-    }
-    R = R1;
-    S = S1;
-    C = C1;
-  }
   for (; m < kmax; ++m) {
-    const float4 e = h[m];
+    const float2 e = ha[m];
     R += e.x;
     S += e.y;
-    C += e.z;
+    C += hc[m].x;
     const float d = Wf - R;
     if (S * S >= thr * (R * d)) consider<true, DIP, false>(R, S, C, d, m, nmax1, mipf, bn, bd, bm);
+  }
+}
+
+// One lane task, weighted curves, when no box can hold every point (the
+// period has more non-empty bins than the widest box) and one point makes a
+// box valid: a box with S != 0 then has points inside and outside, so only
+// R (W - R) > 0 is checked and the counts are not needed.
+template <bool DIP>
+__device__ __forceinline__ void scan_task_weighted_free(const float2 *h, int kmin, int kmax,
+                                                        float Wf, float thr, float &bn, float &bd,
+                                                        int &bm) {
+  float R = 0.0f, S = 0.0f;
+  int m = 0;
+  for (; m < kmin - 1; ++m) {
+    const float2 e = h[m];
+    R += e.x;
+    S += e.y;
+  }
+  bn = 0.0f;
+  bd = 1.0f;
+  bm = -1;
+  for (; m + 4 <= kmax; m += 4) {
+    const float2 e0 = h[m], e1 = h[m + 1], e2 = h[m + 2], e3 = h[m + 3];
+    const float R0 = R + e0.x, S0 = S + e0.y;
+    const float R1 = R0 + e1.x, S1 = S0 + e1.y;
+    const float R2 = R1 + e2.x, S2 = S1 + e2.y;
+    const float R3 = R2 + e3.x, S3 = S2 + e3.y;
+    const float den0 = R0 * (Wf - R0), den1 = R1 * (Wf - R1);
+    const float den2 = R2 * (Wf - R2), den3 = R3 * (Wf - R3);
+    const bool p0 = S0 * S0 >= thr * den0;
+    const bool p1 = S1 * S1 >= thr * den1;
+    const bool p2 = S2 * S2 >= thr * den2;
+    const bool p3 = S3 * S3 >= thr * den3;
+    if (p0 | p1 | p2 | p3) {
+      if (p0) consider<true, DIP, false>(R0, S0, 0.5f, Wf - R0, m, 1.0f, 0.0f, bn, bd, bm);
+      if (p1) consider<true, DIP, false>(R1, S1, 0.5f, Wf - R1, m + 1, 1.0f, 0.0f, bn, bd, bm);
+      if (p2) consider<true, DIP, false>(R2, S2, 0.5f, Wf - R2, m + 2, 1.0f, 0.0f, bn, bd, bm);
+      if (p3) consider<true, DIP, false>(R3, S3, 0.5f, Wf - R3, m + 3, 1.0f, 0.0f, bn, bd, bm);
+    }
+    R = R3;
+    S = S3;
+  }
+  for (; m < kmax; ++m) {
+    const float2 e = h[m];
+    R += e.x;
+    S += e.y;
+    const float d = Wf - R;
+    if (S * S >= thr * (R * d)) consider<true, DIP, false>(R, S, 0.5f, d, m, 1.0f, 0.0f, bn, bd, bm);
   }
 }
 
@@ -422,6 +459,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
   __shared__ double s_f[kTileMax];
   __shared__ unsigned long long s_best[kTileMax];
+  __shared__ int s_nonempty[kTileMax];
   __shared__ long long s_item;
   __shared__ int s_curve;
   __shared__ int s_tile;
@@ -480,6 +518,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     if (tid < np) {
       s_f[tid] = 1.0 / a.periods[cd.p_off + p0 + tid];
       s_best[tid] = 0ull;
+      s_nonempty[tid] = 0;
     }
     __syncthreads();
 
@@ -498,18 +537,22 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
       int t = tid / nb, b = tid - (tid / nb) * nb;
       const int dt = kBlock / nb, db = kBlock - (kBlock / nb) * nb;
       for (; t < np;) {
-        unsigned long long *w = s_hist + ((size_t)t * HB + b) * wpb;
+        unsigned long long *w = s_hist + (size_t)t * HB * wpb + b;
         unsigned long long w0 = w[0];
-        unsigned long long w1 = WEIGHTED ? w[1] : 0ull;
+        unsigned long long w1 = WEIGHTED ? w[HB] : 0ull;
         if (b == nb - 1) {
-          w0 += w[wpb];
-          if (WEIGHTED) w1 += w[wpb + 1];
+          w0 += w[1];
+          if (WEIGHTED) w1 += w[HB + 1];
         }
         const BinWord bw = decode_word(w0, cd.shift);
         if (WEIGHTED) {
-          float4 *o = reinterpret_cast<float4 *>(w);
-          *o = make_float4(int47_to_float(bw.sum) * qscale,
-                           int47_to_float((long long)w1) * qscale, (float)bw.count, 0.0f);
+          // A slot <- (R, S) of the bin, B slot <- (count, 0)
+          *reinterpret_cast<float2 *>(w) =
+              make_float2(int47_to_float(bw.sum) * qscale, int47_to_float((long long)w1) * qscale);
+          *reinterpret_cast<float2 *>(w + HB) = make_float2((float)bw.count, 0.0f);
+          if (bw.count != 0u)
+            __hip_atomic_fetch_add(&s_nonempty[t], 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
           float2 *o = reinterpret_cast<float2 *>(w);
           *o = make_float2((float)bw.count, int47_to_float(bw.sum) * qscale);
@@ -529,10 +572,9 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
       for (int i = tid; i < np * ext; i += kBlock) {
         const int t = i / ext;
         const int e = i - t * ext;
-        unsigned long long *src = s_hist + ((size_t)t * HB + e) * wpb;
-        unsigned long long *dst = s_hist + ((size_t)t * HB + nb + e) * wpb;
-        dst[0] = src[0];
-        if (WEIGHTED) dst[1] = src[1];
+        unsigned long long *src = s_hist + (size_t)t * HB * wpb + e;
+        src[nb] = src[0];
+        if (WEIGHTED) src[HB + nb] = src[HB];
       }
     }
     __syncthreads();
@@ -556,8 +598,11 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         float bn, bd;
         int bm;
         if (WEIGHTED) {
-          const float4 *h = reinterpret_cast<const float4 *>(s_hist) + (size_t)t * HB + j;
-          scan_task_weighted<DIP>(h, kmin, kmax, Wf, thr, nmax1, mipf, bn, bd, bm);
+          const float2 *ha = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HB * 2) + j;
+          if (mip1 && s_nonempty[t] > kmax)
+            scan_task_weighted_free<DIP>(ha, kmin, kmax, Wf, thr, bn, bd, bm);
+          else
+            scan_task_weighted<DIP>(ha, ha + HB, kmin, kmax, Wf, thr, nmax1, mipf, bn, bd, bm);
         } else {
           const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
           if (mip1)
@@ -603,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         // S in the scan's order; R (exact counts for unit weights)
         float R = 0.0f, S = 0.0f;
         if (WEIGHTED) {
-          const float4 *h = reinterpret_cast<const float4 *>(s_hist) + (size_t)t * HB + j;
+          const float2 *h = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HB * 2) + j;
           for (int m = 0; m < k; ++m) {
             R += h[m].x;
             S += h[m].y;
@@ -640,6 +685,235 @@ __global__ void bins_kernel(const double *dt, int64_t n, const double *period, i
   if (i < n) {
     const double f = 1.0 / period[0];
     bins[i] = phase_bin(dt[i], f, (double)nbins, (unsigned)(nbins - 1));
+  }
+}
+
+// ------------------------------------------------------------- detection
+// One workgroup per curve: mean and population deviation of SR (FP64), then
+// peaks largest first with neighbourhood / harmonic suppression tracked in
+// an LDS bitmask.
+__global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
+  extern __shared__ unsigned int s_mask[];
+  __shared__ double sa[kBlock];
+  __shared__ double sb[kBlock];
+  __shared__ unsigned long long s_key;
+  const int c = blockIdx.x;
+  if (c >= a.ncurves) return;
+  const DetectDesc dd = a.desc[c];
+  const int64_t m = dd.nperiods;
+  const float *sr = a.sr + dd.r_off;
+  const double *per = a.periods + dd.p_off;
+  bls_detection *out = reinterpret_cast<bls_detection *>(a.out) + c;
+  const int tid = threadIdx.x;
+
+  double sum = 0.0, mx = 0.0;
+  for (int64_t p = tid; p < m; p += kBlock) sum = sum + (double)sr[p];
+  double dummy = 0.0;
+  block_sum2(sum, dummy, sa, sb);
+  const double mean = sum / (double)m;
+  double ss = 0.0;
+  mx = -INFINITY;
+  for (int64_t p = tid; p < m; p += kBlock) {
+    const double dv = (double)sr[p] - mean;
+    ss = ss + dv * dv;
+    mx = fmax(mx, (double)sr[p]);
+  }
+  block_sum2(ss, dummy, sa, sb);
+  double mn = INFINITY;
+  block_minmax(mn, mx, sa, sb);
+  const double sd = sqrt(ss / (double)m);
+  const double sde = sd > 0.0 ? (mx - mean) / sd : 0.0;
+
+  for (int i = tid; i < a.mask_words; i += kBlock) s_mask[i] = 0u;
+  __syncthreads();
+  const double harm[5] = {1.0, 0.5, 2.0, 1.0 / 3.0, 3.0};
+  int k = 0;
+  for (; k < a.max_peaks; ++k) {
+    if (tid == 0) s_key = 0ull;
+    __syncthreads();
+    unsigned long long best = 0ull;
+    for (int64_t p = tid; p < m; p += kBlock) {
+      const float v = sr[p];
+      if (v > 0.0f && !(s_mask[p >> 5] & (1u << (p & 31)))) {
+        const unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                                       (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+        best = key > best ? key : best;
+      }
+    }
+    if (best) __hip_atomic_fetch_max(&s_key, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    const unsigned long long key = s_key;
+    if (key == 0ull) break;
+    const int64_t pk = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+    const float vk = __uint_as_float((unsigned)(key >> 32));
+    if (tid == 0) {
+      out->peak_index[k] = pk;
+      out->peak_sr[k] = vk;
+      out->peak_sde[k] = sd > 0.0 ? (float)(((double)vk - mean) / sd) : 0.0f;
+    }
+    const double P = per[pk];
+    for (int64_t p = tid; p < m; p += kBlock) {
+      bool off = false;
+      for (int h = 0; h < 5; ++h) {
+        const double cp = harm[h] * P;
+        if (fabs(per[p] - cp) <= a.window * cp) off = true;
+      }
+      if (off)
+        __hip_atomic_fetch_or(&s_mask[p >> 5], 1u << (p & 31), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out->mean_sr = mean;
+    out->std_sr = sd;
+    out->sde = sde;
+    out->npeaks = k;
+    out->candidate = sde >= a.threshold ? 1 : 0;
+    for (int i = k; i < BLS_MAX_PEAKS; ++i) {
+      out->peak_index[i] = -1;
+      out->peak_sr[i] = 0.0f;
+      out->peak_sde[i] = 0.0f;
+    }
+  }
+}
+
+// ------------------------------------------------------- eclipse window
+// Detection efficiency of a cadence.  Per trial period the kept times are
+// folded with the phase bins of the search (nphase bins); every bin keeps the
+// smallest and largest cycle number floor(d f) of the points in it.  The
+// eclipse starting at offset j covers bins j .. j+k-1 of one cycle, the
+// bins past the end of the cycle belonging to the eclipse one cycle earlier,
+// so over its window the eclipse numbers seen are cycle (bins >= j) and
+// cycle - 1 (wrapped bins); two distinct eclipses are observed exactly when
+// the largest such number exceeds the smallest, one when any bin is filled.
+
+__global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
+  __shared__ double sa[kBlock];
+  __shared__ double sb[kBlock];
+  const int c = blockIdx.x;
+  if (c >= a.ncurves) return;
+  WindowDesc *wd = a.desc + c;
+  const int64_t off = wd->n_off, n = wd->n;
+  const int tid = threadIdx.x;
+  double tmin = INFINITY, bad = 0.0, kept = 0.0;
+  for (int64_t i = tid; i < n; i += kBlock) {
+    const double wi = a.w ? a.w[off + i] : 1.0;
+    if (!(wi >= 0.0) || isinf(wi)) {
+      bad = 1.0;
+      continue;
+    }
+    if (wi == 0.0) continue;
+    const double ti = a.t[off + i];
+    if (!isfinite(ti)) {
+      bad = 1.0;
+      continue;
+    }
+    kept = kept + 1.0;
+    tmin = fmin(tmin, ti);
+  }
+  double badp = 0.0;
+  if (wd->check_periods) {
+    for (int64_t i = tid; i < wd->nperiods; i += kBlock) {
+      const double P = a.periods[wd->p_off + i];
+      if (!isfinite(P) || !(P > 0.0)) badp = 1.0;
+    }
+  }
+  block_sum2(bad, kept, sa, sb);
+  double mx = badp;
+  block_minmax(tmin, mx, sa, sb);
+  if (tid == 0) {
+    wd->t0 = tmin;
+    wd->status = bad > 0.0 ? kCurveBadData
+                 : kept < 1.0 ? kCurveTooFew
+                 : mx > 0.0 ? kCurveBadPeriod
+                            : kCurveOk;
+  }
+}
+
+constexpr int kCycleEmptyLo = 0x3fffffff;   // min of an empty bin
+constexpr int kCycleEmptyHi = -0x3fffffff;  // max of an empty bin
+
+__global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
+  extern __shared__ int2 s_mm[];            // [tile][nphase] (min, max cycle)
+  __shared__ double s_f[kTileMax];
+  __shared__ int s_k[kTileMax];
+  __shared__ int s_count[kTileMax];
+  const int tid = threadIdx.x;
+  const int nb = a.nphase;
+  const double nbd = (double)nb;
+  const unsigned nbm1 = (unsigned)(nb - 1);
+
+  for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    int lo = 0, hi = a.ncurves - 1;          // cadence of this item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.desc[mid].item0 <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const WindowDesc wd = a.desc[lo];
+    const int p0 = (int)(item - wd.item0) * a.tile;
+    const int np = min(a.tile, wd.nperiods - p0);
+    int32_t *out = a.observed + wd.r_off + p0;
+    if (wd.status != kCurveOk) {
+      if (tid < np) out[tid] = -1;
+      continue;                              // uniform across the block
+    }
+    if (tid < np) {
+      const double f = 1.0 / a.periods[wd.p_off + p0 + tid];
+      const double kr = __builtin_round(a.duration * f * nbd);
+      s_f[tid] = f;
+      s_k[tid] = kr < 1.0 ? 1 : kr > nbd ? nb : (int)kr;
+      s_count[tid] = 0;
+    }
+    for (int i = tid; i < np * nb; i += kBlock) s_mm[i] = make_int2(kCycleEmptyLo, kCycleEmptyHi);
+    __syncthreads();
+
+    // Fold: cycle numbers per bin.
+    bool over = false;
+    for (int64_t i = tid; i < wd.n; i += kBlock) {
+      const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
+      if (wi == 0.0) continue;
+      const double d = a.t[wd.n_off + i] - wd.t0;
+      for (int t = 0; t < np; ++t) {
+        const double cyc = d * s_f[t];
+        const double e = floor(cyc);
+        const int b = (int)min((unsigned)(int)(__builtin_amdgcn_fract(cyc) * nbd), nbm1);
+        over |= e >= (double)kMaxCycle;
+        const int ei = e >= (double)kMaxCycle ? kMaxCycle : (int)e;
+        int *w2 = reinterpret_cast<int *>(s_mm + t * nb + b);
+        atomicMin(w2, ei);
+        atomicMax(w2 + 1, ei);
+      }
+    }
+    if (over) atomicOr(a.overflow, 1u);
+    __syncthreads();
+
+    // Scan: one task per (period, offset), windows of k bins.
+    const int need2 = a.min_eclipses >= 2;
+    for (int task = tid; task < np * nb; task += kBlock) {
+      const int t = task / nb;
+      const int j = task - t * nb;
+      const int k = s_k[t];
+      const int2 *h = s_mm + t * nb;
+      int lo_c = kCycleEmptyLo, hi_c = kCycleEmptyHi;
+      const int first = min(k, nb - j);      // bins j .. nb-1, same cycle
+      for (int m = 0; m < first; ++m) {
+        const int2 v = h[j + m];
+        lo_c = min(lo_c, v.x);
+        hi_c = max(hi_c, v.y);
+      }
+      for (int m = 0; m < k - first; ++m) {  // wrapped bins: one cycle earlier
+        const int2 v = h[m];
+        lo_c = min(lo_c, v.x - 1);
+        hi_c = max(hi_c, v.y - 1);
+      }
+      const bool seen = need2 ? hi_c > lo_c : hi_c >= lo_c;
+      if (seen) atomicAdd(&s_count[t], 1);
+    }
+    __syncthreads();
+    if (tid < np) out[tid] = s_count[tid];
+    __syncthreads();
   }
 }
 
@@ -703,11 +977,42 @@ int launch_bins(const double *dt, int64_t n, const double *period, int32_t nbins
   return (int)hipGetLastError();
 }
 
+int launch_detect(const DetectArgs &a, void *stream) {
+  if (a.ncurves <= 0) return 0;
+  const size_t lds = (size_t)a.mask_words * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&detect_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(detect_kernel, dim3(a.ncurves), dim3(kBlock), lds, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
 int launch_best_index(unsigned long long *keys, int32_t n, void *stream) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(best_index_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                      keys, n);
   return (int)hipGetLastError();
+}
+
+int launch_window(const WindowArgs &a, int grid, void *stream) {
+  if (a.ncurves <= 0) return 0;
+  hipLaunchKernelGGL(window_prep_kernel, dim3(a.ncurves), dim3(kBlock), 0, (hipStream_t)stream,
+                     a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nitems <= 0) return (int)e;
+  const int lds = a.tile * a.nphase * (int)sizeof(int2);
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&window_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(window_kernel, dim3(grid), dim3(kBlock), (size_t)lds, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int window_blocks_per_cu(int lds_bytes, int *blocks) {
+  const void *fn = reinterpret_cast<const void *>(&window_kernel);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
 }
 
 int search_blocks_per_cu(bool weighted, bool dip_only, int hist_bytes, int *blocks) {

@@ -641,6 +641,9 @@ int bls_plan_destroy(bls_plan *p) {
   if (!p) return BLS_OK;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   drop_graph(p);
+  for (void *d : {(void *)p->d_detect_desc, (void *)p->d_detect_out,
+                  (void *)p->d_window_desc, (void *)p->d_window_flag})
+    free_dev(d);
   for (void *d : {(void *)p->d_curves, (void *)p->d_seg_start, (void *)p->d_seg_curve,
                   (void *)p->d_seg_tile0, (void *)p->d_dt, (void *)p->d_q, (void *)p->d_qw,
                   (void *)p->d_counter, (void *)p->d_t, (void *)p->d_x, (void *)p->d_w,
@@ -755,6 +758,157 @@ int bls_search_device(bls_plan *p, const bls_batch *b, const bls_device_results 
   }
   if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   fill_stats(p, pb, false);
+  return BLS_OK;
+}
+
+int bls_detect_device(bls_plan *p, const bls_batch *b, const float *sr, int32_t max_peaks,
+                      double window, double sde_threshold, bls_detection *out) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!b || !sr || !out || max_peaks < 0 || max_peaks > BLS_MAX_PEAKS || !(window >= 0.0) ||
+      !isfinite(window) || isnan(sde_threshold))
+    return set_error(p, BLS_ERR_INVALID_ARG,
+                     "need batch, sr, out, 0 <= max_peaks <= 16, finite window >= 0");
+  std::string err;
+  std::vector<CurveShape> shapes;
+  int st = validate_batch(p->cfg, *b, false, shapes, err);
+  if (st != BLS_OK) return set_error(p, st, err);
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  const int nc = b->ncurves;
+  std::vector<DetectDesc> dd(nc);
+  int64_t mmax = 0;
+  for (int c = 0; c < nc; ++c) {
+    dd[c].p_off = shapes[c].p_off;
+    dd[c].r_off = shapes[c].r_off;
+    dd[c].nperiods = shapes[c].nperiods;
+    mmax = std::max<int64_t>(mmax, shapes[c].nperiods);
+  }
+  if (mmax > (int64_t(1) << 20))
+    return set_error(p, BLS_ERR_CAPACITY, "detection handles at most 2^20 periods per curve");
+  if (!p->d_detect_desc) {
+    if ((e = device_alloc((void **)&p->d_detect_desc, sizeof(DetectDesc) * p->cfg.max_curves)) ||
+        (e = device_alloc((void **)&p->d_detect_out, sizeof(bls_detection) * p->cfg.max_curves))) {
+      if (p->d_detect_desc) (void)hipFree(p->d_detect_desc);
+      p->d_detect_desc = nullptr;
+      p->d_detect_out = nullptr;
+      return hip_error(p, e, "allocate detection buffers");
+    }
+  }
+  hipStream_t s = p->stream;
+  if ((e = hipMemcpyAsync(p->d_detect_desc, dd.data(), sizeof(DetectDesc) * nc,
+                          hipMemcpyHostToDevice, s)))
+    return hip_error(p, e, "upload detection descriptors");
+  DetectArgs a;
+  a.desc = p->d_detect_desc;
+  a.periods = b->periods;
+  a.sr = sr;
+  a.out = p->d_detect_out;
+  a.ncurves = nc;
+  a.max_peaks = max_peaks;
+  a.window = window;
+  a.threshold = sde_threshold;
+  a.mask_words = (int32_t)std::max<int64_t>(1, (mmax + 31) / 32);
+  if ((e = (hipError_t)launch_detect(a, s))) return hip_error(p, e, "launch detection");
+  if ((e = hipMemcpyAsync(out, p->d_detect_out, sizeof(bls_detection) * nc,
+                          hipMemcpyDeviceToHost, s)) ||
+      (e = hipStreamSynchronize(s)))
+    return hip_error(p, e, "detection");
+  return BLS_OK;
+}
+
+int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, double duration,
+                              int32_t min_eclipses, int32_t *observed) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  char msg[200];
+  if (!b || !observed || b->ncurves < 1 || !b->n_off || !b->times || !b->periods)
+    return set_error(p, BLS_ERR_INVALID_ARG,
+                     "need a batch with ncurves >= 1, n_off, times, periods, and observed");
+  if (nphase < 1 || nphase > BLS_MAX_NBINS || !(duration > 0.0) || !isfinite(duration) ||
+      (min_eclipses != 1 && min_eclipses != 2))
+    return set_error(p, BLS_ERR_INVALID_ARG,
+                     "need 1 <= nphase <= 4096, finite duration > 0, min_eclipses 1 or 2");
+  if (b->ncurves > p->cfg.max_curves) return set_error(p, BLS_ERR_CAPACITY, "too many cadences");
+  if (b->n_off[0] != 0 || (b->p_off && b->p_off[0] != 0) ||
+      (!b->p_off && b->nperiods_shared < 1))
+    return set_error(p, BLS_ERR_INVALID_ARG, "n_off[0] and p_off[0] must be 0, grid non-empty");
+  const int nc = b->ncurves;
+  const int tile = std::max(1, std::min(kTileMax, (32 << 10) / (nphase * 8)));
+  std::vector<WindowDesc> wd(nc);
+  int64_t items = 0, results = 0;
+  for (int c = 0; c < nc; ++c) {
+    WindowDesc &d = wd[c];
+    memset(&d, 0, sizeof d);
+    d.n_off = b->n_off[c];
+    d.n = b->n_off[c + 1] - b->n_off[c];
+    const int64_t np = b->p_off ? b->p_off[c + 1] - b->p_off[c] : b->nperiods_shared;
+    if (d.n < 1 || np < 1 || np > INT32_MAX) {
+      snprintf(msg, sizeof msg, "cadence %d has %lld points and %lld periods (need >= 1 each)", c,
+               (long long)d.n, (long long)np);
+      return set_error(p, BLS_ERR_INVALID_ARG, msg);
+    }
+    d.p_off = b->p_off ? b->p_off[c] : 0;
+    d.r_off = b->p_off ? b->p_off[c] : (int64_t)c * b->nperiods_shared;
+    d.nperiods = (int32_t)np;
+    d.check_periods = (b->p_off || c == 0) ? 1 : 0;
+    d.item0 = items;
+    items += (np + tile - 1) / tile;
+    results += np;
+  }
+  if (b->n_off[nc] > p->cfg.max_points || results > p->cfg.max_periods)
+    return set_error(p, BLS_ERR_CAPACITY, "points or periods exceed the plan's limits");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  if (!p->d_window_desc) {
+    if ((e = device_alloc((void **)&p->d_window_desc, sizeof(WindowDesc) * p->cfg.max_curves)) ||
+        (e = device_alloc((void **)&p->d_window_flag, sizeof(unsigned int)))) {
+      if (p->d_window_desc) (void)hipFree(p->d_window_desc);
+      p->d_window_desc = nullptr;
+      p->d_window_flag = nullptr;
+      return hip_error(p, e, "allocate eclipse-window buffers");
+    }
+  }
+  const int lds = tile * nphase * 8;
+  int per_cu = 0;
+  if ((e = (hipError_t)window_blocks_per_cu(lds, &per_cu)) != hipSuccess)
+    return hip_error(p, e, "window occupancy");
+  const int64_t grid = std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * p->num_cus * 4);
+  hipStream_t s = p->stream;
+  const unsigned int zero = 0;
+  if ((e = hipMemcpyAsync(p->d_window_desc, wd.data(), sizeof(WindowDesc) * nc,
+                          hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(p->d_window_flag, &zero, sizeof zero, hipMemcpyHostToDevice, s)))
+    return hip_error(p, e, "upload window descriptors");
+  WindowArgs a;
+  a.desc = p->d_window_desc;
+  a.ncurves = nc;
+  a.tile = tile;
+  a.nitems = items;
+  a.t = b->times;
+  a.w = b->weights;
+  a.periods = b->periods;
+  a.observed = observed;
+  a.nphase = nphase;
+  a.min_eclipses = min_eclipses;
+  a.duration = duration;
+  a.overflow = p->d_window_flag;
+  if ((e = (hipError_t)launch_window(a, (int)grid, s))) return hip_error(p, e, "launch window");
+  unsigned int flag = 0;
+  if ((e = hipMemcpyAsync(wd.data(), p->d_window_desc, sizeof(WindowDesc) * nc,
+                          hipMemcpyDeviceToHost, s)) ||
+      (e = hipMemcpyAsync(&flag, p->d_window_flag, sizeof flag, hipMemcpyDeviceToHost, s)) ||
+      (e = hipStreamSynchronize(s)))
+    return hip_error(p, e, "eclipse window");
+  for (int c = 0; c < nc; ++c) {
+    if (wd[c].status != kCurveOk) {
+      snprintf(msg, sizeof msg, "cadence %d: %s", c,
+               wd[c].status == kCurveBadData     ? "non-finite kept time or a bad weight"
+               : wd[c].status == kCurveBadPeriod ? "a trial period is not finite and > 0"
+                                                 : "no point with positive weight");
+      return set_error(p, BLS_ERR_INVALID_ARG, msg);
+    }
+  }
+  if (flag)
+    return set_error(p, BLS_ERR_CAPACITY, "a cadence spans more than 2^29 cycles of a period");
   return BLS_OK;
 }
 

@@ -67,6 +67,14 @@ struct bls_plan {
   int32_t *d_j = nullptr, *d_k = nullptr;
   int64_t *d_best = nullptr;
 
+  // detection buffers (allocated on first use)
+  bls::DetectDesc *d_detect_desc = nullptr;
+  void *d_detect_out = nullptr;
+
+  // eclipse-window buffers (allocated on first use)
+  bls::WindowDesc *d_window_desc = nullptr;
+  unsigned int *d_window_flag = nullptr;
+
   // pinned host descriptors
   bls::CurveDesc *h_curves = nullptr;
   int64_t *h_seg_start = nullptr;

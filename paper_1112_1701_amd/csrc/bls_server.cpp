@@ -29,7 +29,10 @@ thread_local std::string g_server_create_error;
 
 struct Req {
   uint64_t ticket = 0;
+  // inputs: in the pinned pool when it had room (async copies), else here
   std::vector<double> t, x, w, per;
+  size_t pin_off = Arena::kFail;
+  const double *pt = nullptr, *px = nullptr, *pw = nullptr, *pper = nullptr;
   bool weighted = false;
   int32_t nbins = 0, kmin = 0, kmax = 0;
   int64_t n = 0, np = 0;
@@ -85,6 +88,8 @@ struct bls_server {
   bool buf_busy[kTickBuffers] = {};
 
   Arena pts_arena, per_arena;
+  char *h_pool = nullptr;   // pinned staging for request inputs
+  Arena pool_arena;
   std::vector<Req *> slots;
   std::deque<Req *> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
@@ -162,11 +167,11 @@ hipError_t start_request(bls_server *s, Req *r) {
   hipStream_t st = s->stream;
   hipError_t e;
   const size_t n = (size_t)r->n, np = (size_t)r->np;
-  if ((e = hipMemcpyAsync(s->d_t + r->pt_off, r->t.data(), n * 8, hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(s->d_x + r->pt_off, r->x.data(), n * 8, hipMemcpyHostToDevice, st)) ||
+  if ((e = hipMemcpyAsync(s->d_t + r->pt_off, r->pt, n * 8, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(s->d_x + r->pt_off, r->px, n * 8, hipMemcpyHostToDevice, st)) ||
       (r->weighted &&
-       (e = hipMemcpyAsync(s->d_w + r->pt_off, r->w.data(), n * 8, hipMemcpyHostToDevice, st))) ||
-      (e = hipMemcpyAsync(s->d_per + r->pr_off, r->per.data(), np * 8, hipMemcpyHostToDevice,
+       (e = hipMemcpyAsync(s->d_w + r->pt_off, r->pw, n * 8, hipMemcpyHostToDevice, st))) ||
+      (e = hipMemcpyAsync(s->d_per + r->pr_off, r->pper, np * 8, hipMemcpyHostToDevice,
                           st)) ||
       (e = hipMemcpyAsync(s->d_curves + r->slot, &d, sizeof d, hipMemcpyHostToDevice, st)))
     return e;
@@ -309,6 +314,10 @@ void scheduler(bls_server *s) {
         r->finished = true;
         s->slots[r->slot] = nullptr;
         s->pts_arena.release(r->pt_off);
+        if (r->pin_off != Arena::kFail) {
+          s->pool_arena.release(r->pin_off);  // its copies finished long ago
+          r->pin_off = Arena::kFail;
+        }
         s->per_arena.release(r->pr_off);
         if (r->status == BLS_OK) {
           s->completed++;
@@ -511,6 +520,15 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
   s->pts_arena.reset(P, kArenaAlign);
   s->per_arena.reset(Q, kArenaAlign);
   s->slots.assign(M, nullptr);
+  {
+    // pinned staging: a quarter of the device arena, at most 1 GiB; requests
+    // that do not fit are staged in pageable memory instead
+    const size_t pool = (size_t)std::min<int64_t>(cfg.arena_bytes / 4, int64_t(1) << 30);
+    if (hipHostMalloc((void **)&s->h_pool, pool, 0) == hipSuccess)
+      s->pool_arena.reset(pool, 256);
+    else
+      s->h_pool = nullptr;
+  }
   s->lds_budget = default_tiles(false).lds_budget;
   // about 40 launches' worth of work per second at full rate keeps launch
   // overhead negligible while new requests wait at most a few milliseconds
@@ -565,10 +583,39 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
   r->kmin = cs.kmin;
   r->kmax = cs.kmax;
   r->weighted = q->weights != nullptr;
-  r->t.assign(q->times, q->times + q->n);
-  r->x.assign(q->flux, q->flux + q->n);
-  if (r->weighted) r->w.assign(q->weights, q->weights + q->n);
-  r->per.assign(q->periods, q->periods + q->nperiods);
+  {
+    const size_t n8 = (size_t)q->n * 8, p8 = (size_t)q->nperiods * 8;
+    const size_t need = 3 * ((n8 + 255) & ~size_t(255)) + p8;
+    size_t off = Arena::kFail;
+    if (s->h_pool) {
+      std::lock_guard<std::mutex> g(s->mu);
+      off = s->pool_arena.alloc(need);
+    }
+    if (off != Arena::kFail) {
+      char *base = s->h_pool + off;
+      const size_t step = (n8 + 255) & ~size_t(255);
+      double *dt_ = (double *)base, *dx = (double *)(base + step),
+             *dw = (double *)(base + 2 * step), *dp = (double *)(base + 3 * step);
+      memcpy(dt_, q->times, n8);
+      memcpy(dx, q->flux, n8);
+      if (r->weighted) memcpy(dw, q->weights, n8);
+      memcpy(dp, q->periods, p8);
+      r->pin_off = off;
+      r->pt = dt_;
+      r->px = dx;
+      r->pw = r->weighted ? dw : nullptr;
+      r->pper = dp;
+    } else {
+      r->t.assign(q->times, q->times + q->n);
+      r->x.assign(q->flux, q->flux + q->n);
+      if (r->weighted) r->w.assign(q->weights, q->weights + q->n);
+      r->per.assign(q->periods, q->periods + q->nperiods);
+      r->pt = r->t.data();
+      r->px = r->x.data();
+      r->pw = r->weighted ? r->w.data() : nullptr;
+      r->pper = r->per.data();
+    }
+  }
   const int wpb = r->weighted ? 2 : 1;
   const int per_period = (r->nbins + std::max(r->kmax - 1, 1)) * 8 * wpb;
   int T = std::max(1, s->lds_budget / per_period);
@@ -581,10 +628,16 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
   r->evals = (double)r->nbins * nw * (double)r->np;
 
   std::lock_guard<std::mutex> g(s->mu);
-  if (s->device_error) return srv_error(s, BLS_ERR_DEVICE, "server stopped after a device error");
-  if (!s->pts_arena.fits_ever((size_t)r->n) || !s->per_arena.fits_ever((size_t)r->np) ||
-      per_period > s->max_lds - 1024)
-    return srv_error(s, BLS_ERR_CAPACITY, "request larger than the server's device arena");
+  int reject = BLS_OK;
+  if (s->device_error)
+    reject = srv_error(s, BLS_ERR_DEVICE, "server stopped after a device error");
+  else if (!s->pts_arena.fits_ever((size_t)r->n) || !s->per_arena.fits_ever((size_t)r->np) ||
+           per_period > s->max_lds - 1024)
+    reject = srv_error(s, BLS_ERR_CAPACITY, "request larger than the server's device arena");
+  if (reject != BLS_OK) {
+    if (r->pin_off != Arena::kFail) s->pool_arena.release(r->pin_off);
+    return reject;
+  }
   r->ticket = s->next_ticket++;
   r->submit_s = now_s(s);
   *ticket = r->ticket;
@@ -738,6 +791,7 @@ int bls_server_destroy(bls_server *s) {
     if (s->ev_e[b]) (void)hipEventDestroy(s->ev_e[b]);
   }
   if (s->h_curves) (void)hipHostFree(s->h_curves);
+  if (s->h_pool) (void)hipHostFree(s->h_pool);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;

@@ -20,4 +20,6 @@ from .lightcurves import (  # noqa: F401
     uniform_batch,
     uneven_batch,
     small_curve,
+    survey_cadence,
+    cadence_batch,
 )

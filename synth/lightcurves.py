@@ -22,6 +22,11 @@ Workload recipes (sizes per the benchmark configurations):
             sigma 0.003, every curve with a box (q U(0.005, 0.05), depth
             log-U(0.002, 0.02), P log-U(0.1, 20)); 100000 shared periods
             0.1-20 d; 1000 bins; q in [0.005, 0.05].
+* cadence:  observing runs of single fields (eclipse detection efficiency):
+            U{30..90} nights, each lost to weather with probability 0.3; on a
+            clear night a 4.5-h window opening 0.1-0.15 d after the night's
+            integer HJD holds exposures every U(15, 25) min; 64 fields share
+            100000 log periods 0.1-10 d, 1000 trial epochs, eclipses 0.02 d.
 * serving:  Poisson arrivals; each request N log-U[500, 20000], U{5000..100000}
             periods in 0.2-10 d, U{200..1000} bins, q in [0.01, 0.10], 20%
             with a box.
@@ -297,3 +302,40 @@ def small_curve(seed: int, n: int, nperiods: int = 64, nbins: int = 64,
                          weighted=weighted)
     return LightCurve(t, x, w, log_period_grid(pmin, pmax, nperiods), nbins,
                       qmin, qmax, tr)
+
+
+def survey_cadence(rng: np.random.Generator, nights: int = 60,
+                   weather: float = 0.3, hours: float = 4.5,
+                   cadence_min=(15.0, 25.0),
+                   t_start: float = T_START) -> np.ndarray:
+    """Exposure times of one field's run (Table 1 cadence, weather losses)."""
+    out = []
+    for d in range(nights):
+        if rng.uniform() < weather:
+            continue
+        t = t_start + d + 0.1 + rng.uniform(0.0, 0.05)
+        end = t + hours / 24.0
+        while t < end:
+            out.append(t)
+            t += rng.uniform(*cadence_min) / 1440.0
+    if not out:                      # keep at least one exposure
+        out.append(t_start + 0.1)
+    return np.asarray(out, np.float64)
+
+
+def cadence_batch(ncadences: int = 64, nperiods: int = 100000,
+                  seed: int = _BASE_SEED + 6, pmin: float = 0.1,
+                  pmax: float = 10.0) -> Batch:
+    """Many fields' cadences on one shared log period grid (times only)."""
+    ss = np.random.SeedSequence(seed)
+    ts = []
+    for child in ss.spawn(ncadences):
+        rng = np.random.default_rng(child)
+        ts.append(survey_cadence(rng, nights=int(rng.integers(30, 91))))
+    n = np.array([t.shape[0] for t in ts], np.int64)
+    n_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    t = np.concatenate(ts)
+    return Batch(t, np.zeros_like(t), None, n_off,
+                 log_period_grid(pmin, pmax, nperiods), None,
+                 np.full(ncadences, 2, np.int32), np.full(ncadences, 0.1),
+                 np.full(ncadences, 0.1))

@@ -44,7 +44,8 @@ def test_struct_layouts_match_c():
     structs = {"bls_plan_config": L.BlsPlanConfig, "bls_batch": L.BlsBatch,
                "bls_results": L.BlsResults,
                "bls_device_results": L.BlsDeviceResults,
-               "bls_call_stats": L.BlsCallStats}
+               "bls_call_stats": L.BlsCallStats,
+               "bls_detection": L.BlsDetection}
     text = open(HEADER).read()
     for opt, cls in (("bls_request", L.BlsRequest),
                      ("bls_result", L.BlsResult),

@@ -294,3 +294,47 @@ def test_device_api_reports_bad_period(bls):
         with pytest.raises(bls.BlsError) as ei:
             bls.bls_synchronize(p.handle)
         assert "trial period" in str(ei.value)
+
+
+def test_detection_statistics(bls):
+    """GPU detection on the GPU's periodogram equals the oracle's detection
+    on the same SR values (identical inputs: identical peaks); end to end it
+    agrees with the oracle's detection on the oracle's own periodogram."""
+    import torch
+    b = synth.uniform_batch(8, 1500, 4000, 200, seed=81, inj_prob=0.5)
+    dev = torch.device("cuda:0")
+    _say("detection")
+    m = b.periods.size
+    t = torch.tensor(b.t, device=dev)
+    x = torch.tensor(b.x, device=dev)
+    per = torch.tensor(b.periods, device=dev)
+    outs = [torch.empty(m * 8, device=dev, dtype=torch.float32),
+            torch.empty(m * 8, device=dev, dtype=torch.float32),
+            torch.empty(m * 8, device=dev, dtype=torch.int32),
+            torch.empty(m * 8, device=dev, dtype=torch.int32),
+            torch.empty(8, device=dev, dtype=torch.int64)]
+    with bls.Plan(max_curves=8, max_points=1 << 16, max_periods=1 << 16) as p:
+        bls.bls_search_device(p.handle, b.n_off, t, x, None, per, None, 200,
+                              0.01, 0.1, *outs)
+        bls.bls_synchronize(p.handle)
+        det = bls.bls_detect_device(p.handle, b.n_off, per, None, 200, 0.01,
+                                    0.1, outs[0], max_peaks=6, window=0.01,
+                                    sde_threshold=6.0)
+    sr = outs[0].cpu().numpy()
+    for c in range(8):
+        g = det[c]
+        src = sr[c * m:(c + 1) * m].astype(np.float64)
+        o = oracle.detect(src, b.periods, max_peaks=6, window=0.01,
+                          threshold=6.0)
+        assert np.array_equal(g["peak_index"], o["peak_index"]), c
+        for k in ("mean", "std", "sde"):
+            assert abs(g[k if k == "sde" else k + "_sr"] - o[k]) <= \
+                1e-12 * max(abs(o[k]), 1e-30), (c, k)
+        assert g["candidate"] == o["candidate"]
+        lc = b.curve(c)
+        oo = _orc(lc)
+        oe = oracle.detect(oo.sr, b.periods, max_peaks=6, window=0.01,
+                           threshold=6.0)
+        assert abs(g["sde"] - oe["sde"]) <= 1e-5 * oe["sde"]
+        assert g["peak_index"][0] in np.flatnonzero(
+            oo.sr >= (1 - 1e-5) * oo.sr.max())
