@@ -72,6 +72,11 @@ def _load():
         ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
         ctypes.c_double, ctypes.c_int32, P, P, P, P, P, P]
     lib.bls_oracle_variability.restype = ctypes.c_int
+    lib.bls_oracle_unbinned.argtypes = [
+        P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+        P, P, P, P, P]
+    lib.bls_oracle_unbinned.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -245,3 +250,32 @@ def variability(x, w, n_off, mag, chip_off, nmagbins, origin=0.0, width=0.1,
         raise OracleError("oracle rejected the input (status %d)" % st)
     return dict(rms=rms, bin=b, flag=f, mean=bm.reshape(nk, nmagbins),
                 std=bs.reshape(nk, nmagbins), count=bc.reshape(nk, nmagbins))
+
+
+def unbinned(t, x, w, periods, qmin, qmax, *, min_in_points=1,
+             dip_only=False, nthreads=0):
+    """Unbinned periodogram of one light curve (readings U1-U3).
+
+    Returns a dict: sr, depth [nperiods] float64; first, last [nperiods]
+    int32 input indices of the best box's first and last points in phase
+    order (-1 where no box); best_index.
+    """
+    lib = _load()
+    t = _f64(t)
+    x = _f64(x)
+    w = None if w is None else _f64(w)
+    periods = _f64(periods)
+    n, m = t.shape[0], periods.shape[0]
+    sr = np.empty(m)
+    depth = np.empty(m)
+    first = np.empty(m, np.int32)
+    last = np.empty(m, np.int32)
+    best = ctypes.c_int64(-1)
+    st = lib.bls_oracle_unbinned(
+        _ptr(t), _ptr(x), _ptr(w), n, _ptr(periods), m, float(qmin),
+        float(qmax), int(min_in_points), int(bool(dip_only)), int(nthreads),
+        _ptr(sr), _ptr(depth), _ptr(first), _ptr(last), ctypes.byref(best))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    return dict(sr=sr, depth=depth, first=first, last=last,
+                best_index=int(best.value))

@@ -697,3 +697,172 @@ int bls_oracle_variability(const double *x, const double *w,
     free(next);
     return BLS_ORACLE_OK;
 }
+
+/*
+ * Unbinned variant: box edges fall between data points instead of on a
+ * phase-bin grid, so every subset of points that some box of duty cycle in
+ * [qmin, qmax] can hold is tried (the range of durations and phases of
+ * section 2.2.2 taken to the limit of the data, as in the unbinned form of
+ * the cited statistic).  Readings, beyond R2, R3 (phase only, no bin), R5,
+ * R6 and the statistic:
+ *   U1  kept points are ordered by phase, ties by input order;
+ *   U2  a box [a, a + q) of phase (cyclic) holds a cyclic run of m
+ *       consecutive points of that order, 1 <= m <= n - 1, starting at
+ *       sorted position r; with prev, first, last, next the positions
+ *       r - 1, r, r + m - 1, r + m (mod n) and forward phase distances
+ *       (one added when the step passes the end of the order), some box
+ *       with q in [qmin, qmax] holds exactly that run iff
+ *         dist(prev, first) > 0, dist(last, next) > 0,
+ *         span = dist(first, last) < qmax and gap = dist(prev, next) > qmin
+ *       (gap = 1 when prev and next are the same point);
+ *   U3  the best box has the largest S^2/(R (W - R)); ties go to the
+ *       smaller m, then the smaller r; first_point and last_point are the
+ *       input indices of its first and last points (-1 if none).
+ */
+typedef struct {
+    double ph;
+    int64_t k;      /* index among kept points */
+} ph_key;
+
+static int cmp_ph(const void *a, const void *b)
+{
+    const ph_key *x = (const ph_key *)a, *y = (const ph_key *)b;
+    if (x->ph < y->ph)
+        return -1;
+    if (x->ph > y->ph)
+        return 1;
+    return (x->k > y->k) - (x->k < y->k);
+}
+
+/* Forward phase distance from sorted position i to j (U2). */
+static double fwd(const ph_key *o, int64_t i, int64_t j)
+{
+    if (j > i)
+        return o[j].ph - o[i].ph;
+    return (o[j].ph + 1.0) - o[i].ph;
+}
+
+int bls_oracle_unbinned(const double *t, const double *x, const double *w,
+                        int64_t n, const double *periods, int64_t nperiods,
+                        double qmin, double qmax, int32_t min_in_points,
+                        int32_t dip_only, int32_t nthreads, double *sr,
+                        double *depth, int32_t *first_point,
+                        int32_t *last_point, int64_t *best_index)
+{
+    if (nperiods < 1 || periods == NULL || min_in_points < 1 ||
+        !(qmin > 0.0) || !(qmax < 1.0) || !(qmin <= qmax))
+        return BLS_ORACLE_INVALID;
+    for (int64_t p = 0; p < nperiods; ++p)
+        if (!isfinite(periods[p]) || !(periods[p] > 0.0))
+            return BLS_ORACLE_INVALID;
+    kept_curve kc;
+    bls_oracle_prep pr;
+    int st = prepare(t, x, w, n, &kc, &pr);
+    if (st != BLS_ORACLE_OK)
+        return st;
+    const int64_t m = kc.n;
+    int64_t *orig = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    double *p_sr = (double *)malloc((size_t)nperiods * sizeof(double));
+    if (!orig || !p_sr) {
+        free(orig);
+        free(p_sr);
+        free_kept(&kc);
+        return BLS_ORACLE_NOMEM;
+    }
+    for (int64_t i = 0, k = 0; i < n; ++i)
+        if (!w || w[i] != 0.0)
+            orig[k++] = i;
+    int failed = 0;
+
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        ph_key *o = (ph_key *)malloc((size_t)m * sizeof(ph_key));
+        if (!o) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        }
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+        for (int64_t p = 0; p < nperiods; ++p) {
+            if (!o)
+                continue;
+            double f = 1.0 / periods[p];
+            for (int64_t i = 0; i < m; ++i) {
+                double c = kc.d[i] * f;
+                o[i].ph = c - floor(c);
+                o[i].k = i;
+            }
+            qsort(o, (size_t)m, sizeof(ph_key), cmp_ph);
+            double bv = 0.0, bS = 0.0, bR = 0.0;
+            int64_t bm = -1, br = -1;
+            for (int64_t r = 0; r < m; ++r) {
+                int64_t prev = (r + m - 1) % m;
+                if (!(fwd(o, prev, r) > 0.0))
+                    continue;
+                double R = 0.0, S = 0.0;
+                for (int64_t len = 1; len <= m - 1; ++len) {
+                    int64_t last = (r + len - 1) % m;
+                    int64_t next = (r + len) % m;
+                    int64_t q = o[last].k;
+                    R = R + kc.w[q];
+                    S = S + kc.w[q] * kc.y[q];
+                    double span = len == 1 ? 0.0 : fwd(o, r, last);
+                    if (!(span < qmax))
+                        break;
+                    if (!(fwd(o, last, next) > 0.0))
+                        continue;
+                    double gap = prev == next ? 1.0 : fwd(o, prev, next);
+                    if (!(gap > qmin))
+                        continue;
+                    if (len < min_in_points)
+                        continue;
+                    if (dip_only && !(S < 0.0))
+                        continue;
+                    double den = R * (pr.W - R);
+                    if (!(den > 0.0))
+                        continue;
+                    double v = (S * S) / den;
+                    if (!(v > 0.0))
+                        continue;
+                    if (v > bv || (v == bv && (len < bm ||
+                                               (len == bm && r < br)))) {
+                        bv = v;
+                        bS = S;
+                        bR = R;
+                        bm = len;
+                        br = r;
+                    }
+                }
+            }
+            p_sr[p] = sqrt(bv);
+            if (sr)
+                sr[p] = p_sr[p];
+            if (depth)
+                depth[p] = bm < 0 ? NAN : -bS * pr.W / (bR * (pr.W - bR));
+            if (first_point)
+                first_point[p] = bm < 0 ? -1 : (int32_t)orig[o[br].k];
+            if (last_point)
+                last_point[p] =
+                    bm < 0 ? -1 : (int32_t)orig[o[(br + bm - 1) % m].k];
+        }
+        free(o);
+    }
+    if (!failed && best_index) {
+        int64_t bi = 0;
+        for (int64_t p = 1; p < nperiods; ++p)
+            if (p_sr[p] > p_sr[bi])
+                bi = p;
+        *best_index = bi;
+    }
+    free(orig);
+    free(p_sr);
+    free_kept(&kc);
+    return failed ? BLS_ORACLE_NOMEM : BLS_ORACLE_OK;
+}

@@ -125,6 +125,21 @@ int bls_oracle_variability(const double *x, const double *w,
                            int32_t *flag, double *bin_mean, double *bin_std,
                            int32_t *bin_count);
 
+/*
+ * Unbinned variant (readings U1-U3 in bls_oracle.c): boxes are the cyclic
+ * runs of phase-sorted kept points that some box of duty cycle in
+ * [qmin, qmax] holds exactly.  Inputs as bls_oracle_search without nbins.
+ * Outputs [nperiods] (any may be NULL): sr, depth, first_point and
+ * last_point (input indices of the best box's first and last points in
+ * phase order, -1 if none); best_index as reading R8.
+ */
+int bls_oracle_unbinned(const double *t, const double *x, const double *w,
+                        int64_t n, const double *periods, int64_t nperiods,
+                        double qmin, double qmax, int32_t min_in_points,
+                        int32_t dip_only, int32_t nthreads, double *sr,
+                        double *depth, int32_t *first_point,
+                        int32_t *last_point, int64_t *best_index);
+
 #ifdef __cplusplus
 }
 #endif
