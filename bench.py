@@ -12,7 +12,8 @@ FP64 CPU oracle timed on a bounded sample of the same workload.
 --suite: one JSON line per workload (plain, uniform, uneven, long baseline):
 batched throughput, the plain per-curve GPU form for comparison, and the
 oracle; then the serving workload swept over Poisson arrival rates with
-p50/p99 latency.
+p50/p99 latency; then the eclipse-window, variability and unbinned
+workloads, each with its kernel time, roofline and oracle.
 """
 from __future__ import annotations
 
@@ -161,12 +162,42 @@ def time_plain(bls, db, max_curves, budget_s=5.0):
     return {"value": done_pp / el, "curves": ncur, "seconds": el}
 
 
-def roofline(pp, evals, k_ms):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_kernel_uniform4096_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1112_1701_amd", "csrc", "bls_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per search-kernel launch from the committed counter runs.
+
+    The file records the counters' bytes per launch and the SHA-256 of the
+    kernel source they were taken on; once the source differs the figure no
+    longer describes this kernel and None is returned.
+    """
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(pp, evals, k_ms, traffic=None):
     ops = OPS_PER_TRIAL_POINT * pp + OPS_PER_BOX_EVAL * evals
     achieved = ops / (k_ms * 1e-3) / 1e12
     peak = PEAK_VALU_OPS / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic}
 
 
 def headline(args):
@@ -213,7 +244,7 @@ def headline(args):
         "launch": {"grid": kst["grid"], "block": kst["block"],
                    "lds_bytes": kst["lds_bytes"],
                    "work_items": kst["work_items"]},
-        "roofline": roofline(pp, evals, k_ms),
+        "roofline": roofline(pp, evals, k_ms, measured_traffic()),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -296,6 +327,187 @@ def suite_serving(bls, rates, pool_size, max_requests, seconds):
     return recs
 
 
+# Algorithmic operations of the other workloads (per unit, stated in the
+# design notes): eclipse window: per point x period the fold (multiply,
+# floor, fract, multiply, truncate) and two LDS min/max updates, per
+# (period, trial epoch) one window decision (min, max, compare, count);
+# unbinned search: per point x period the fold and rank (10), per run step
+# the two exact sums, span and gap distances, S^2, R (W - R), compare (8).
+OPS_WINDOW_PP, OPS_WINDOW_EPOCH = 7, 4
+OPS_UNBINNED_PP, OPS_UNBINNED_STEP = 10, 8
+HBM_PEAK_GBS = 8000.0
+
+
+def _alu_roofline(ops, k_ms):
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    peak = PEAK_VALU_OPS / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+
+
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def suite_window(args, bls):
+    """Eclipse detection efficiency of 64 field cadences x 100000 periods."""
+    import numpy as np
+    import torch
+
+    import synth
+    log("suite window")
+    b = synth.cadence_batch()
+    dev = torch.device("cuda:0")
+    t = torch.tensor(b.t, device=dev)
+    per = torch.tensor(b.periods, device=dev)
+    obs = torch.empty(b.ncurves * b.periods.size, device=dev,
+                      dtype=torch.int32)
+    with bls.Plan(max_curves=b.ncurves, max_points=b.total_points(),
+                  max_periods=obs.numel()) as p:
+        kms, wall = [], []
+        for r in range(args.suite_steps + 1):
+            t0 = time.perf_counter()
+            bls.bls_eclipse_window_device(p.handle, b.n_off, t, per, None,
+                                          1000, 0.02, 2, obs)
+            wall.append((time.perf_counter() - t0) * 1e3)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+            st = bls.bls_last_stats(p.handle)
+    k_ms, w_ms = _median(kms[1:]), _median(wall[1:])
+    pp, dec = st["trial_points"], st["box_evals"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = b.periods[::50]
+        t0 = time.perf_counter()
+        done = 0.0
+        for c in range(b.ncurves):
+            tc = b.curve(c).t
+            oracle.eclipse_window(tc, None, sub, 1000, 0.02, 2)
+            done += float(tc.size) * sub.size
+            if time.perf_counter() - t0 > args.cpu_budget / 3:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": done / el, "unit": "trial-periods*points/s",
+               "cores": os.cpu_count(), "kind": "oracle",
+               "sample": "%d cadences x every 50th period" % (c + 1)}
+    return {"workload": "eclipse window: 64 field cadences x 100000 log "
+                        "periods 0.1-10 d, 1000 epochs, 0.02 d eclipses, "
+                        "two required",
+            "points": int(b.total_points()), "trial_points": pp,
+            "epoch_decisions": dec, "kernel_ms": k_ms, "call_ms": w_ms,
+            "trial_points_per_s": pp / (k_ms * 1e-3),
+            "launch": {"grid": st["grid"], "lds_bytes": st["lds_bytes"],
+                       "work_items": st["work_items"]},
+            "roofline": _alu_roofline(OPS_WINDOW_PP * pp +
+                                      OPS_WINDOW_EPOCH * dec, k_ms),
+            "cpu_baseline": cpu}
+
+
+def suite_variability(args, bls):
+    """High-variability pre-search of one 100000-star pointing."""
+    import torch
+
+    import synth
+    log("suite variability")
+    b, mag, chip_off, _ = synth.variability_field()
+    dev = torch.device("cuda:0")
+    nc, nk = b.ncurves, len(chip_off) - 1
+    x = torch.tensor(b.x, device=dev)
+    m = torch.tensor(mag, device=dev)
+    f64, i32 = torch.float64, torch.int32
+    out = dict(rms=torch.empty(nc, device=dev, dtype=f64),
+               bin=torch.empty(nc, device=dev, dtype=i32),
+               flag=torch.empty(nc, device=dev, dtype=i32),
+               bin_mean=torch.empty(nk * 60, device=dev, dtype=f64),
+               bin_std=torch.empty(nk * 60, device=dev, dtype=f64),
+               bin_count=torch.empty(nk * 60, device=dev, dtype=i32))
+    with bls.Plan(max_curves=nc, max_points=b.total_points(),
+                  max_periods=16) as p:
+        kms, wall = [], []
+        for r in range(args.suite_steps + 3):
+            t0 = time.perf_counter()
+            bls.bls_variability_device(p.handle, b.n_off, x, None, m,
+                                       chip_off, 60, out, origin=14.0)
+            wall.append((time.perf_counter() - t0) * 1e3)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+    k_ms, w_ms = _median(kms[1:]), _median(wall[1:])
+    npts = int(b.total_points())
+    nbytes = 8.0 * npts + 40.0 * nc
+    achieved = nbytes / (k_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.variability(b.x, None, b.n_off, mag, chip_off, 60,
+                           origin=14.0)
+        el = time.perf_counter() - t0
+        cpu = {"value": npts / el, "unit": "points/s", "cores": 1,
+               "kind": "oracle", "sample": "the whole pointing"}
+    return {"workload": "variability pre-search: 100000 stars on 11 chips, "
+                        "140-300 epochs, 60 bins of 0.1 mag",
+            "points": npts, "stars": nc, "kernel_ms": k_ms, "call_ms": w_ms,
+            "points_per_s": npts / (k_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "cpu_baseline": cpu}
+
+
+def suite_unbinned(args, bls):
+    """Unbinned search: 8 noisy copies of the plain curve, 5000 periods."""
+    import numpy as np
+    import torch
+
+    import synth
+    log("suite unbinned")
+    lc = synth.config1()
+    ncur = 8
+    rng = np.random.default_rng(3)
+    xs = [lc.x + rng.normal(0, 0.001, lc.n) for _ in range(ncur)]
+    n_off = np.arange(0, (ncur + 1) * lc.n, lc.n, dtype=np.int64)
+    dev = torch.device("cuda:0")
+    t = torch.tensor(np.tile(lc.t, ncur), device=dev)
+    x = torch.tensor(np.concatenate(xs), device=dev)
+    per = torch.tensor(lc.periods, device=dev)
+    mres = ncur * lc.periods.size
+    outs = [torch.empty(mres, device=dev, dtype=torch.float32),
+            torch.empty(mres, device=dev, dtype=torch.float32),
+            torch.empty(mres, device=dev, dtype=torch.int32),
+            torch.empty(mres, device=dev, dtype=torch.int32),
+            torch.empty(ncur, device=dev, dtype=torch.int64)]
+    with bls.Plan(max_curves=ncur, max_points=int(n_off[-1]),
+                  max_periods=mres) as p:
+        kms = []
+        for r in range(args.suite_steps + 1):
+            bls.bls_search_unbinned_device(p.handle, n_off, t, x, None, per,
+                                           None, lc.qmin, lc.qmax, *outs)
+            bls.bls_synchronize(p.handle)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+        st = bls.bls_last_stats(p.handle)
+    k_ms = _median(kms[1:])
+    pp, steps = st["trial_points"], st["box_evals"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = lc.periods[::10]
+        t0 = time.perf_counter()
+        oracle.unbinned(lc.t, xs[0], None, sub, lc.qmin, lc.qmax)
+        el = time.perf_counter() - t0
+        cpu = {"value": lc.n * sub.size / el,
+               "unit": "trial-periods*points/s", "cores": os.cpu_count(),
+               "kind": "oracle", "sample": "1 curve x every 10th period"}
+    return {"workload": "unbinned search: 8 x N=1000, 5000 log periods "
+                        "0.2-10 d, q 0.01-0.10",
+            "trial_points": pp, "run_steps_est": steps, "kernel_ms": k_ms,
+            "trial_points_per_s": pp / (k_ms * 1e-3),
+            "launch": {"grid": st["grid"], "lds_bytes": st["lds_bytes"],
+                       "work_items": st["work_items"]},
+            "roofline": _alu_roofline(OPS_UNBINNED_PP * pp +
+                                      OPS_UNBINNED_STEP * steps, k_ms),
+            "cpu_baseline": cpu}
+
+
 def suite(args):
     import paper_1112_1701_amd as bls
     import synth
@@ -305,7 +517,12 @@ def suite(args):
     gens = {"plain": lambda: _as_batch(synth.config1()),
             "uniform": synth.config2, "uneven": synth.config3,
             "long": synth.config4}
+    extra = {"window": suite_window, "variability": suite_variability,
+             "unbinned": suite_unbinned}
     for name in names:
+        if name in extra:
+            print(json.dumps(extra[name](args, bls)), flush=True)
+            continue
         if name == "serving":
             recs = suite_serving(bls, [float(r) for r in
                                        args.rates.split(",")],
@@ -337,7 +554,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--suite", action="store_true")
-    ap.add_argument("--workloads", default="plain,uniform,uneven,long,serving")
+    ap.add_argument("--workloads", default="plain,uniform,uneven,long,"
+                    "serving,window,variability,unbinned")
     ap.add_argument("--suite-steps", type=int, default=3)
     ap.add_argument("--rates", default="100,500,1000,2000,5000")
     ap.add_argument("--pool", type=int, default=300)

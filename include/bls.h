@@ -200,6 +200,38 @@ int bls_last_error(const bls_plan *plan, char *buf, size_t len);
 const char *bls_status_string(int status);
 
 /*
+ * Unbinned search: box edges fall between data points instead of on a
+ * phase-bin grid (the range of durations and phases of section 2.2.2 taken
+ * to the limit of the data).  Per curve and trial period, the kept points
+ * are ordered by phase (t0 = min kept time, phase = frac((t - t0) / P) in
+ * FP64, ties by input order); a box is a cyclic run of m consecutive points
+ * of that order, 1 <= m <= n - 1, that some box of duty cycle q in
+ * [qmin, qmax] of the period holds exactly: the run does not split equal
+ * phases, its phase span (first to last point) is below qmax and the phase
+ * distance between its two outside neighbours exceeds qmin (1 when they are
+ * the same point).  Validity, statistic and tie rules are those of the
+ * binned search, ties going to the smaller m, then to the earlier start in
+ * phase order.
+ * batch: as for bls_search_device (device times, flux, weights, periods);
+ * nbins is ignored and qmin/qmax are phase fractions; at most 4096 points
+ * per curve.  out: device arrays [results]: FP32 SR and depth, and the
+ * input indices (within the curve) of the best box's first and last points
+ * in phase order (-1 where no box); best_index per curve.  Asynchronous on
+ * the plan's stream: bls_synchronize reports invalid data.  Errors:
+ * INVALID_ARG, CAPACITY (a curve above 4096 points, plan limits), DEVICE.
+ */
+typedef struct {
+    float *sr;
+    float *depth;
+    int32_t *first_point;
+    int32_t *last_point;
+    int64_t *best_index;
+} bls_unbinned_results;
+
+int bls_search_unbinned_device(bls_plan *plan, const bls_batch *batch,
+                               const bls_unbinned_results *out);
+
+/*
  * Detection statistics of each curve's periodogram (the step after the
  * search: the signal detection efficiency of the cited BLS statistic and
  * the strongest peaks).  Per curve, over its m trial periods:
@@ -260,6 +292,59 @@ int bls_eclipse_window_device(bls_plan *plan, const bls_batch *cadences,
                               int32_t min_eclipses, int32_t *observed);
 
 /*
+ * High-variability pre-search (the step before the box search, section
+ * 2.2.1): stars much more variable than others of similar magnitude on the
+ * same chip are flagged.  Per star c (a curve of the batch):
+ *   rms[c] = population RMS about the mean of its kept values (weight > 0,
+ *   all if weights is NULL), unweighted; a star with no kept value, a
+ *   non-finite kept value or a bad weight is invalid (rms NaN, bin -1,
+ *   flag -1);
+ *   bin[c] = floor((mag[c] - origin) / width) when in [0, nmagbins), else
+ *   -1 (also for a non-finite magnitude).
+ * Per (chip k, bin b), over the valid stars of chip k in bin b (chip k holds
+ * stars chip_off[k] .. chip_off[k+1]-1): the clipped set starts as all of
+ * them; a round takes its mean and population deviation and drops members
+ * outside [mean - clip_sigma dev, mean + clip_sigma dev]; rounds repeat until
+ * one drops nothing or max_iter rounds have dropped members; bin_mean,
+ * bin_std and bin_count describe the final set (NaN, NaN, 0 if the bin has
+ * no star).  When bin_count >= min_stars every star of the bin with
+ * rms > bin_mean + flag_sigma bin_std gets flag 1; other valid stars 0.
+ * The paper's choices: width 0.1 mag, flag_sigma 2.
+ */
+typedef struct {
+    int32_t nchips;
+    int32_t nmagbins;           /* 1 .. 4096 bins per chip                  */
+    const int64_t *chip_off;    /* host [nchips + 1]; chip_off[nchips] ==
+                                   ncurves, non-decreasing                  */
+    const double *mag;          /* DEVICE [ncurves] reference magnitudes    */
+    double origin;              /* lower edge of bin 0                      */
+    double width;               /* bin width (> 0)                          */
+    double clip_sigma;          /* > 0                                      */
+    double flag_sigma;          /* >= 0                                     */
+    int32_t max_iter;           /* 0 .. 64 clipping rounds                  */
+    int32_t min_stars;          /* >= 1                                     */
+} bls_variability_config;
+
+/* Device result arrays (all required). */
+typedef struct {
+    double *rms;                /* [ncurves]                                */
+    int32_t *bin;               /* [ncurves]                                */
+    int32_t *flag;              /* [ncurves]                                */
+    double *bin_mean;           /* [nchips * nmagbins], chip-major          */
+    double *bin_std;            /* [nchips * nmagbins]                      */
+    int32_t *bin_count;         /* [nchips * nmagbins]                      */
+} bls_variability_results;
+
+/* curves: a bls_batch whose flux and weights are DEVICE pointers (times,
+ * periods, nbins, qmin, qmax are ignored; curves may be empty).
+ * Synchronous on the plan's stream.  Errors: INVALID_ARG, CAPACITY (more
+ * curves than max_curves, nmagbins or max_iter above their limits), DEVICE,
+ * NO_MEMORY. */
+int bls_variability_device(bls_plan *plan, const bls_batch *curves,
+                           const bls_variability_config *cfg,
+                           const bls_variability_results *out);
+
+/*
  * Diagnostic: the phase bin the search kernel assigns to each point of one
  * curve (unit weights) at one trial period, computed by the same device
  * code (t0 = min time, d = t - t0, f = 1/P, bin = min(trunc(frac(d f)
@@ -270,9 +355,13 @@ int bls_eclipse_window_device(bls_plan *plan, const bls_batch *cadences,
 int bls_debug_phase_bins(bls_plan *plan, const double *times, int64_t n,
                          double period, int32_t nbins, int32_t *bins);
 
-/* Timing and shape of the plan's last search call. */
+/* Timing and shape of the plan's last search, unbinned-search,
+ * eclipse-window or variability call (for the last two, search_ms covers
+ * their kernels; trial_points is points x periods, resp. points; box_evals
+ * is periods x nphase epoch decisions, resp. stars; for the unbinned search
+ * box_evals estimates the run steps as sum n * qmax * n * nperiods). */
 typedef struct {
-    double search_ms;       /* search kernel, device time (HIP events)      */
+    double search_ms;       /* main kernel(s), device time (HIP events)     */
     double total_ms;        /* whole call as queued on the stream           */
     double trial_points;    /* sum over curves of N_c * nperiods_c          */
     double box_evals;       /* sum over curves of nbins * nwidths * nperiods */

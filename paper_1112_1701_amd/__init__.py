@@ -25,6 +25,8 @@ from .api import (  # noqa: F401
     bls_debug_phase_bins,
     bls_detect_device,
     bls_eclipse_window_device,
+    bls_variability_device,
+    bls_search_unbinned_device,
     bls_server_config_init,
     bls_server_create,
     bls_server_submit,

@@ -76,6 +76,26 @@ class BlsDetection(C.Structure):
                 ("peak_sde", C.c_float * BLS_MAX_PEAKS)]
 
 
+class BlsUnbinnedResults(C.Structure):
+    _fields_ = [("sr", C.c_void_p), ("depth", C.c_void_p),
+                ("first_point", C.c_void_p), ("last_point", C.c_void_p),
+                ("best_index", C.c_void_p)]
+
+
+class BlsVariabilityConfig(C.Structure):
+    _fields_ = [("nchips", C.c_int32), ("nmagbins", C.c_int32),
+                ("chip_off", C.c_void_p), ("mag", C.c_void_p),
+                ("origin", C.c_double), ("width", C.c_double),
+                ("clip_sigma", C.c_double), ("flag_sigma", C.c_double),
+                ("max_iter", C.c_int32), ("min_stars", C.c_int32)]
+
+
+class BlsVariabilityResults(C.Structure):
+    _fields_ = [("rms", C.c_void_p), ("bin", C.c_void_p),
+                ("flag", C.c_void_p), ("bin_mean", C.c_void_p),
+                ("bin_std", C.c_void_p), ("bin_count", C.c_void_p)]
+
+
 class BlsRequest(C.Structure):
     _fields_ = [("times", C.c_void_p), ("flux", C.c_void_p),
                 ("weights", C.c_void_p), ("n", C.c_int64),
@@ -153,6 +173,8 @@ def load():
         "bls_debug_phase_bins": (C.c_int, [P, P, I64, D, I32, P]),
         "bls_detect_device": (C.c_int, [P, P, P, I32, D, D, P]),
         "bls_eclipse_window_device": (C.c_int, [P, P, I32, D, I32, P]),
+        "bls_variability_device": (C.c_int, [P, P, P, P]),
+        "bls_search_unbinned_device": (C.c_int, [P, P, P]),
     }
     optional = {
         "bls_server_config_init": (None, [P]),

@@ -213,6 +213,24 @@ def bls_search_device(plan, n_off, times, flux, weights, periods, p_off,
            plan)
 
 
+def bls_search_unbinned_device(plan, n_off, times, flux, weights, periods,
+                               p_off, qmin, qmax, sr, depth, first_point,
+                               last_point, best_index):
+    """Unbinned search on device tensors; asynchronous on the plan stream.
+
+    As bls_search_device without nbins; first_point/last_point (int32)
+    receive the curve-relative input indices of each best box's first and
+    last points in phase order.  Call bls_synchronize before reading.
+    """
+    ba = _batch(n_off, times, flux, weights, periods, p_off, 2, qmin, qmax,
+                device=True)
+    o = L.BlsUnbinnedResults(sr.data_ptr(), depth.data_ptr(),
+                             first_point.data_ptr(), last_point.data_ptr(),
+                             best_index.data_ptr())
+    _check(L.load().bls_search_unbinned_device(plan, C.byref(ba.struct),
+                                               C.byref(o)), plan)
+
+
 def bls_detect_device(plan, n_off, periods, p_off, nbins, qmin, qmax, sr,
                       max_peaks=8, window=0.01, sde_threshold=7.0):
     """Detection statistics of each curve's periodogram (device SR tensor).
@@ -253,6 +271,35 @@ def bls_eclipse_window_device(plan, n_off, times, periods, p_off, nphase,
     _check(L.load().bls_eclipse_window_device(
         plan, C.byref(ba.struct), int(nphase), float(duration),
         int(min_eclipses), C.c_void_p(observed.data_ptr())), plan)
+
+
+def bls_variability_device(plan, n_off, flux, weights, mag, chip_off,
+                           nmagbins, out, origin=0.0, width=0.1,
+                           clip_sigma=3.0, max_iter=5, flag_sigma=2.0,
+                           min_stars=3):
+    """High-variability pre-search on device tensors.
+
+    flux, weights (or None) and mag are device tensors (float64); out is a
+    dict of device tensors: rms (f64), bin and flag (int32) per curve;
+    bin_mean, bin_std (f64) and bin_count (int32) per (chip, bin).  n_off
+    and chip_off are host arrays.  Synchronous.
+    """
+    ba = _batch(n_off, flux, flux, weights, flux, None, 2, 0.1, 0.1,
+                device=True)
+    co = np.ascontiguousarray(chip_off, dtype=np.int64)
+    cfg = L.BlsVariabilityConfig()
+    cfg.nchips = co.shape[0] - 1
+    cfg.nmagbins = int(nmagbins)
+    cfg.chip_off = co.ctypes.data
+    cfg.mag = mag.data_ptr()
+    cfg.origin, cfg.width = float(origin), float(width)
+    cfg.clip_sigma, cfg.flag_sigma = float(clip_sigma), float(flag_sigma)
+    cfg.max_iter, cfg.min_stars = int(max_iter), int(min_stars)
+    res = L.BlsVariabilityResults()
+    for k in ("rms", "bin", "flag", "bin_mean", "bin_std", "bin_count"):
+        setattr(res, k, out[k].data_ptr())
+    _check(L.load().bls_variability_device(plan, C.byref(ba.struct),
+                                           C.byref(cfg), C.byref(res)), plan)
 
 
 class Plan:

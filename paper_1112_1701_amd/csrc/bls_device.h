@@ -15,8 +15,9 @@ namespace bls {
 
 constexpr int kBlock = 256;        // threads per workgroup
 constexpr int kTileMax = 32;       // largest period tile
-constexpr int kPPT = 8;            // points held in registers per thread
+constexpr int kPPT = 4;            // points held in registers per thread
 constexpr int kQBitsMax = 30;      // fixed-point magnitude bits per point
+constexpr int kMaxParts = 8;       // work partitions (one per XCD)
 
 enum CurveStatus : int32_t {
   kCurveOk = 0,
@@ -52,6 +53,9 @@ struct CurveDesc {
   int32_t es;           // exponent of the S fixed-point scale
   int32_t ew;           // exponent of the weight fixed-point scale
   int32_t pad;
+  // ---- unbinned search only (host)
+  double qlo;           // duty-cycle limits of a box, in phase
+  double qhi;
 };
 
 struct PrepArgs {
@@ -78,14 +82,35 @@ struct SearchArgs {
   int32_t nseg;
   int32_t min_in_points;
   int64_t nitems;
-  unsigned long long *counter;  // work counter, zeroed before the launch
+  unsigned long long *counter;  // kMaxParts work counters, zeroed before the launch
   float *sr;
   float *depth;
   int32_t *jstart;
   int32_t *kwidth;
   unsigned long long *best_key;  // per curve, zeroed before the launch
   int32_t hist_bytes;         // dynamic LDS for histograms
+  int32_t ucap;               // unbinned search: largest curve (points)
+  // Work partitions: items [part_begin[x], part_begin[x+1]) belong to
+  // partition x, which workgroups with blockIdx.x % nparts == x drain first
+  // (workgroups are dispatched to the XCDs round-robin, so a partition's
+  // curves stay in one XCD's L2); counter[x] counts its items taken.
+  int32_t nparts;
+  int32_t pad_parts;
+  int64_t part_begin[kMaxParts + 1];
 };
+
+// One partition over all items (callers without an XCD split).
+inline void single_partition(SearchArgs &a) {
+  a.nparts = 1;
+  a.pad_parts = 0;
+  for (int x = 0; x <= kMaxParts; ++x) a.part_begin[x] = x == 0 ? 0 : a.nitems;
+}
+
+// Unbinned search: LDS bytes for curves of up to n points.
+int unbinned_lds_bytes(int n, bool weighted);
+int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream);
+int unbinned_blocks_per_cu(bool weighted, bool dip_only, int lds_bytes, int *blocks);
+constexpr int kUnbinnedMaxPoints = 4096;
 
 struct DetectDesc {
   int64_t p_off;     // first trial period of the curve
@@ -136,6 +161,37 @@ struct WindowArgs {
 constexpr int kMaxCycle = 1 << 29;
 
 int launch_window(const WindowArgs &a, int grid, void *stream);
+
+// High-variability pre-search.
+constexpr int kVarMaxBins = 4096;   // magnitude bins per chip
+constexpr int kVarMaxIter = 64;     // clipping rounds
+
+struct VarArgs {
+  int32_t ncurves;
+  int32_t nchips;
+  int32_t nmagbins;
+  int32_t max_iter;
+  int32_t min_stars;
+  int32_t pad;
+  const int64_t *n_off;     // device [ncurves + 1]
+  const int64_t *chip_off;  // device [nchips + 1]
+  const double *x;
+  const double *w;          // nullptr: unit weights
+  const double *mag;
+  double origin;
+  double width;
+  double clip_sigma;
+  double flag_sigma;
+  double *rms;              // [ncurves]
+  int32_t *bin;             // [ncurves]
+  int32_t *flag;            // [ncurves]
+  double *bin_mean;         // [nchips * nmagbins]
+  double *bin_std;
+  int32_t *bin_count;
+  uint8_t *alive;           // [ncurves] scratch: in the clipped set
+};
+
+int launch_variability(const VarArgs &a, void *stream);
 int window_blocks_per_cu(int lds_bytes, int *blocks);
 
 // Launch wrappers (bls_kernels.hip).  All return hipError_t as int.

@@ -454,6 +454,24 @@ __device__ __forceinline__ void scan_task_weighted_free(const float2 *h, int kmi
   }
 }
 
+// Next work item of a persistent workgroup (thread 0 only): items of its
+// own partition first, then of the others in turn; -1 once all are taken.
+// done_mask remembers the partitions found empty.
+__device__ inline long long next_item(const SearchArgs &a, unsigned &done_mask) {
+  const int np = a.nparts;
+  const int home = (int)(blockIdx.x % (unsigned)np);
+  for (int k = 0; k < np; ++k) {
+    const int x = home + k < np ? home + k : home + k - np;
+    if (done_mask & (1u << x)) continue;
+    const unsigned long long it =
+        __hip_atomic_fetch_add(a.counter + x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long item = a.part_begin[x] + (long long)it;
+    if (item < a.part_begin[x + 1]) return item;
+    done_mask |= 1u << x;
+  }
+  return -1;
+}
+
 template <bool WEIGHTED, bool DIP>
 __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
@@ -466,27 +484,27 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
 
   const int tid = threadIdx.x;
   constexpr int wpb = WEIGHTED ? 2 : 1;
+  unsigned done_mask = 0u;
 
   for (;;) {
     if (tid == 0) {
-      const unsigned long long it =
-          __hip_atomic_fetch_add(a.counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_item = (long long)it;
-      if ((long long)it < a.nitems) {
+      const long long it = next_item(a, done_mask);
+      s_item = it;
+      if (it >= 0) {
         int lo = 0, hi = a.nseg - 1;  // last s with seg_start[s] <= it
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (a.seg_start[mid] <= (long long)it)
+          if (a.seg_start[mid] <= it)
             lo = mid;
           else
             hi = mid - 1;
         }
         s_curve = a.seg_curve[lo];
-        s_tile = a.seg_tile0[lo] + (int)((long long)it - a.seg_start[lo]);
+        s_tile = a.seg_tile0[lo] + (int)(it - a.seg_start[lo]);
       }
     }
     __syncthreads();
-    if (s_item >= a.nitems) break;
+    if (s_item < 0) break;
     // Item values are uniform: keep them (and the curve record) scalar.
     const int c = __builtin_amdgcn_readfirstlane(s_curve);
     const int tile = __builtin_amdgcn_readfirstlane(s_tile);
@@ -495,9 +513,12 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const CurveDesc cd = a.curves[c];
     const int p0 = tile * cd.tile;
     const int np = min(cd.tile, cd.nperiods - p0);
-    if (np <= 0) continue;
-
-    if (cd.status != kCurveOk) {
+    // Every item reaches the one barrier at the end of the loop body (no
+    // `continue`: a second way into the loop header that skips thread 0's
+    // fetch lets the compiler keep the other lanes circling the header
+    // barrier without it).
+    if (np <= 0) {
+    } else if (cd.status != kCurveOk) {
       for (int t = tid; t < np; t += kBlock) {
         const int64_t r = cd.r_off + p0 + t;
         a.sr[r] = NAN;
@@ -505,9 +526,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         a.jstart[r] = -1;
         a.kwidth[r] = -1;
       }
-      continue;
-    }
-
+    } else {
     const int nb = cd.nbins;
     const int kmin = cd.kmin;
     const int kmax = cd.kmax;
@@ -671,10 +690,21 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         a.jstart[r] = j;
         a.kwidth[r] = k;
       }
-      const unsigned long long ckey = ((unsigned long long)__float_as_uint(srf) << 32) |
-                                      (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-      __hip_atomic_fetch_max(a.best_key + c, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_best[t] = ((unsigned long long)__float_as_uint(srf) << 32) |
+                  (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
     }
+    __syncthreads();
+    // One global update per item: the tile's largest (SR, ~period) key.
+    if (tid < 64) {
+      unsigned long long ck = tid < np ? s_best[tid] : 0ull;
+      for (int o = 16; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(ck, o, 64);
+        ck = other > ck ? other : ck;
+      }
+      if (tid == 0)
+        __hip_atomic_fetch_max(a.best_key + c, ck, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    }  // valid item
     __syncthreads();
   }
 }
@@ -855,10 +885,11 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
     const int p0 = (int)(item - wd.item0) * a.tile;
     const int np = min(a.tile, wd.nperiods - p0);
     int32_t *out = a.observed + wd.r_off + p0;
+    // One barrier sequence for every item: invalid cadences fall through to
+    // the barrier at the end of the loop body rather than `continue`.
     if (wd.status != kCurveOk) {
       if (tid < np) out[tid] = -1;
-      continue;                              // uniform across the block
-    }
+    } else {
     if (tid < np) {
       const double f = 1.0 / a.periods[wd.p_off + p0 + tid];
       const double kr = __builtin_round(a.duration * f * nbd);
@@ -896,30 +927,493 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
       const int j = task - t * nb;
       const int k = s_k[t];
       const int2 *h = s_mm + t * nb;
+      // The window is decided as soon as it holds the required eclipses:
+      // lo/hi only move apart, so stop there.
       int lo_c = kCycleEmptyLo, hi_c = kCycleEmptyHi;
+      const int gap = need2 ? 1 : 0;
       const int first = min(k, nb - j);      // bins j .. nb-1, same cycle
-      for (int m = 0; m < first; ++m) {
+      for (int m = 0; m < first && hi_c - lo_c < gap; ++m) {
         const int2 v = h[j + m];
         lo_c = min(lo_c, v.x);
         hi_c = max(hi_c, v.y);
       }
-      for (int m = 0; m < k - first; ++m) {  // wrapped bins: one cycle earlier
-        const int2 v = h[m];
+      for (int m = 0; m < k - first && hi_c - lo_c < gap; ++m) {  // wrapped:
+        const int2 v = h[m];                                       // cycle - 1
         lo_c = min(lo_c, v.x - 1);
         hi_c = max(hi_c, v.y - 1);
       }
-      const bool seen = need2 ? hi_c > lo_c : hi_c >= lo_c;
+      const bool seen = hi_c - lo_c >= gap;
       if (seen) atomicAdd(&s_count[t], 1);
     }
     __syncthreads();
     if (tid < np) out[tid] = s_count[tid];
+    }  // valid cadence
     __syncthreads();
   }
 }
 
+// ------------------------------------------------- variability pre-search
+// Stability of every star (population RMS of its kept values) and its
+// magnitude bin, then per (chip, bin) an iterated sigma-clipped mean and
+// deviation and the stars above it by flag_sigma deviations.  All sums run
+// in FP64 in a fixed lane order combined by a fixed butterfly, so results do
+// not depend on scheduling.
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int wave_isum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wave per star: the mean, then the mean squared deviation (two passes,
+// as the definition reads).  A star of up to 512 values is loaded once into
+// registers (8 per lane, all loads in flight together) and both passes run
+// there; longer stars take the second pass from memory again.
+constexpr int kVarRegs = 8;
+
+__global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (c >= a.ncurves) return;
+  const int64_t off = a.n_off[c], n = a.n_off[c + 1] - off;
+  const double *x = a.x + off;
+  const double *w = a.w ? a.w + off : nullptr;
+  int cnt = 0, bad = 0;
+  double s = 0.0;
+  double xv[kVarRegs];
+  bool kv[kVarRegs];
+#pragma unroll
+  for (int u = 0; u < kVarRegs; ++u) {   // lanes past the end keep nothing
+    xv[u] = 0.0;
+    kv[u] = false;
+  }
+  for (int64_t i0 = lane; i0 < n; i0 += 64 * kVarRegs) {
+#pragma unroll
+    for (int u = 0; u < kVarRegs; ++u) {
+      const int64_t i = i0 + 64 * u;
+      xv[u] = i < n ? x[i] : 0.0;
+      const double wi = i < n ? (w ? w[i] : 1.0) : 0.0;
+      if (!(wi >= 0.0) || isinf(wi)) bad = 1;
+      kv[u] = wi > 0.0 && !isinf(wi);
+    }
+#pragma unroll
+    for (int u = 0; u < kVarRegs; ++u) {
+      if (!kv[u]) continue;
+      if (!isfinite(xv[u])) bad = 1;
+      s = s + xv[u];
+      ++cnt;
+    }
+  }
+  s = wave_sum(s);
+  cnt = wave_isum(cnt);
+  bad = wave_isum(bad);
+  const double mu = s / (double)cnt;
+  double ss = 0.0;
+  if (!bad && cnt > 0) {
+    if (n <= 64 * kVarRegs) {
+#pragma unroll
+      for (int u = 0; u < kVarRegs; ++u) {
+        if (!kv[u]) continue;
+        const double dv = xv[u] - mu;
+        ss = ss + dv * dv;
+      }
+    } else {
+      for (int64_t i = lane; i < n; i += 64) {
+        const double wi = w ? w[i] : 1.0;
+        if (wi == 0.0) continue;
+        const double dv = x[i] - mu;
+        ss = ss + dv * dv;
+      }
+    }
+  }
+  ss = wave_sum(ss);
+  if (lane != 0) return;
+  if (bad || cnt == 0) {
+    a.rms[c] = __longlong_as_double(0x7ff8000000000000ll);
+    a.bin[c] = -1;
+    a.flag[c] = -1;
+    return;
+  }
+  a.rms[c] = sqrt(ss / (double)cnt);
+  a.flag[c] = 0;
+  int b = -1;
+  const double m = a.mag[c];
+  if (isfinite(m)) {
+    const double q = floor((m - a.origin) / a.width);
+    if (q >= 0.0 && q < (double)a.nmagbins) b = (int)q;
+  }
+  a.bin[c] = b;
+}
+
+constexpr int kVarListCap = 1024;   // members kept in LDS per (chip, bin)
+
+// Visit the members of one (chip, bin) in star order: from the LDS list
+// when it holds them all, else by rescanning the chip's stars.
+template <class F>
+__device__ inline void for_members(const int *list, int cnt0, int c0, int c1, int b,
+                                   const int32_t *bin, int lane, F f) {
+  if (cnt0 <= kVarListCap) {
+    for (int i = lane; i < cnt0; i += 64) f(list[i]);
+  } else {
+    for (int st = c0 + lane; st < c1; st += 64)
+      if (bin[st] == b) f(st);
+  }
+}
+
+// One wave per (chip, bin).
+__global__ __launch_bounds__(kBlock) void var_clip_kernel(VarArgs a) {
+  __shared__ int s_list[kBlock / 64][kVarListCap];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t task = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (task >= (int64_t)a.nchips * a.nmagbins) return;
+  const int k = (int)(task / a.nmagbins);
+  const int b = (int)(task - (int64_t)k * a.nmagbins);
+  const int c0 = (int)a.chip_off[k], c1 = (int)a.chip_off[k + 1];
+  int *list = s_list[wv];
+
+  // Members in star order (ballot compaction), all alive; eight chunks of
+  // bin numbers are loaded together per round.
+  int cnt0 = 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int base = c0; base < c1; base += 64 * 8) {
+    int bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int st = base + 64 * u + lane;
+      bv[u] = st < c1 ? a.bin[st] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int st = base + 64 * u + lane;
+      const bool mem = bv[u] == b;
+      const unsigned long long mask = __ballot(mem);
+      if (mem) {
+        const int pos = cnt0 + __popcll(mask & below);
+        if (pos < kVarListCap) list[pos] = st;
+        a.alive[st] = 1;
+      }
+      cnt0 += __popcll(mask);
+    }
+  }
+  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+  if (cnt0 == 0) {
+    if (lane == 0) {
+      a.bin_mean[task] = qnan;
+      a.bin_std[task] = qnan;
+      a.bin_count[task] = 0;
+    }
+    return;
+  }
+  int cnt = cnt0;
+  double mu = 0.0, sd = 0.0;
+  for (int it = 0;; ++it) {
+    double s = 0.0;
+    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
+      if (a.alive[st]) s = s + a.rms[st];
+    });
+    mu = wave_sum(s) / (double)cnt;
+    double ss = 0.0;
+    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
+      if (a.alive[st]) {
+        const double dv = a.rms[st] - mu;
+        ss = ss + dv * dv;
+      }
+    });
+    sd = sqrt(wave_sum(ss) / (double)cnt);
+    if (it >= a.max_iter) break;
+    const double lo = mu - a.clip_sigma * sd, hi = mu + a.clip_sigma * sd;
+    int drop = 0;
+    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
+      if (a.alive[st]) {
+        const double v = a.rms[st];
+        if (!(v >= lo && v <= hi)) {
+          a.alive[st] = 0;
+          ++drop;
+        }
+      }
+    });
+    drop = wave_isum(drop);
+    if (drop == 0) break;
+    cnt -= drop;
+  }
+  if (lane == 0) {
+    a.bin_mean[task] = mu;
+    a.bin_std[task] = sd;
+    a.bin_count[task] = cnt;
+  }
+  if (cnt < a.min_stars) return;
+  const double thr = mu + a.flag_sigma * sd;
+  for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
+    if (a.rms[st] > thr) a.flag[st] = 1;
+  });
+}
+
+// ------------------------------------------------------ unbinned search
+// Box edges between data points: per period the kept points are put in
+// phase order (ties by index) and every cyclic run that some box with duty
+// cycle in [qlo, qhi] holds exactly is scored.  The order is found without a
+// comparison sort: a counting sort on a fine phase grid (about one point per
+// cell) groups the points, and each point's rank is its cell's start plus
+// the number of cell mates that precede it.  Sums over a run are exact
+// int64 sums of the fixed-point values of the prep pass.
+
+__host__ __device__ inline int pow2_at_least(int n) {
+  int m = 1;
+  while (m < n) m <<= 1;
+  return m;
+}
+
+// Forward phase distance from sorted position i to j (one cycle added when
+// the step passes the end of the order).
+__device__ inline double fwd_dist(const double *ph, int i, int j) {
+  return j > i ? ph[j] - ph[i] : (ph[j] + 1.0) - ph[i];
+}
+
+template <bool WEIGHTED, bool DIP>
+__global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  __shared__ long long s_item;
+  __shared__ int s_curve;
+  __shared__ int s_per;
+  __shared__ unsigned long long s_vbits;
+  __shared__ unsigned int s_tie;
+  __shared__ long long s_bestS, s_bestR;
+  __shared__ long long s_wsum[kBlock / 64];
+  __shared__ int s_part[kBlock];
+
+  const int tid = threadIdx.x;
+  const int N = a.ucap;
+  const int Mc = pow2_at_least(N);
+  double *ph_u = reinterpret_cast<double *>(s_raw);
+  double *sph = ph_u + N;
+  int *sq = reinterpret_cast<int *>(sph + N);
+  int *sidx = sq + N;
+  int *grp = sidx + N;
+  int *cnt = grp + N;
+  int *sw = cnt + Mc + 1;   // weighted only
+
+  unsigned done_mask = 0u;
+  for (;;) {
+    if (tid == 0) {
+      const long long it = next_item(a, done_mask);
+      s_item = it;
+      if (it >= 0) {
+        int lo = 0, hi = a.nseg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (a.seg_start[mid] <= it)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        s_curve = a.seg_curve[lo];
+        s_per = (int)(it - a.seg_start[lo]);
+      }
+    }
+    __syncthreads();
+    if (s_item < 0) break;
+    const int c = __builtin_amdgcn_readfirstlane(s_curve);
+    const int p = __builtin_amdgcn_readfirstlane(s_per);
+    __syncthreads();
+
+    const CurveDesc cd = a.curves[c];
+    const int64_t r_out = cd.r_off + p;
+    // Every item, valid or not, reaches the one barrier at the end of the
+    // loop body: a `continue` here would give the loop header a second way
+    // in that skips thread 0's fetch, and the compiler may then keep the
+    // other lanes circling the header barrier without thread 0.
+    if (cd.status != kCurveOk) {
+      if (tid == 0) {
+        a.sr[r_out] = NAN;
+        a.depth[r_out] = NAN;
+        a.jstart[r_out] = -1;
+        a.kwidth[r_out] = -1;
+      }
+    } else {
+    const int n = (int)cd.n;
+    const int M = pow2_at_least(n);
+    const double Md = (double)M;
+    const double f = 1.0 / a.periods[cd.p_off + p];
+    const double *dt = a.dt + cd.n_off;
+    const int32_t *q = a.q + cd.n_off;
+    const int32_t *qw = WEIGHTED ? a.qw + cd.n_off : nullptr;
+
+    // Phases and fine-grid cells; dropped points go to the extra cell M.
+    for (int i = tid; i <= M; i += kBlock) cnt[i] = 0;
+    if (tid == 0) {
+      s_vbits = 0ull;
+      s_tie = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    long long wsum = 0;
+    for (int i = tid; i < n; i += kBlock) {
+      const bool kept = WEIGHTED ? qw[i] >= 0 : true;
+      const double ph = __builtin_amdgcn_fract(dt[i] * f);
+      ph_u[i] = kept ? ph : 2.0;
+      const int cell = kept ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      atomicAdd(&cnt[cell], 1);
+      if (WEIGHTED && kept) wsum += qw[i];
+    }
+    __syncthreads();
+    // Exclusive scan of the M + 1 cell counts (runs per thread, then a
+    // sequential pass over the 256 run totals).
+    {
+      const int per = (M + 1 + kBlock - 1) / kBlock;
+      const int b0 = min(M + 1, tid * per), b1 = min(M + 1, b0 + per);
+      int run = 0;
+      for (int b = b0; b < b1; ++b) run += cnt[b];
+      s_part[tid] = run;
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < kBlock; ++i) {
+          const int v = s_part[i];
+          s_part[i] = acc;
+          acc += v;
+        }
+      }
+      __syncthreads();
+      int acc = s_part[tid];
+      for (int b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        cnt[b] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+    // Scatter into cells (any order inside a cell); cnt becomes cell ends.
+    for (int i = tid; i < n; i += kBlock) {
+      const double ph = ph_u[i];
+      const int cell = ph < 1.5 ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      grp[atomicAdd(&cnt[cell], 1)] = i;
+    }
+    __syncthreads();
+    // Rank = cell start + cell mates before this point in (phase, index).
+    for (int i = tid; i < n; i += kBlock) {
+      const double ph = ph_u[i];
+      const int cell = ph < 1.5 ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      const int b = cell == 0 ? 0 : cnt[cell - 1];
+      const int e = cnt[cell];
+      int rank = b;
+      for (int k = b; k < e; ++k) {
+        const int j = grp[k];
+        const double pj = ph_u[j];
+        rank += (pj < ph || (pj == ph && j < i)) ? 1 : 0;
+      }
+      sph[rank] = ph;
+      sq[rank] = q[i];
+      sidx[rank] = i;
+      if (WEIGHTED) sw[rank] = qw[i];
+    }
+    long long W = 0;
+    if (WEIGHTED) {
+      for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+      if ((tid & 63) == 0) s_wsum[tid >> 6] = wsum;
+    }
+    __syncthreads();
+    const int nk = M == 0 ? 0 : cnt[M - 1];  // kept points come first
+    if (WEIGHTED) {
+      for (int k = 0; k < kBlock / 64; ++k) W += s_wsum[k];
+    } else {
+      W = nk;
+    }
+    const double Wd = (double)W;
+    const double qlo = cd.qlo, qhi = cd.qhi;
+
+    // Runs from every start position.
+    double bv = 0.0;
+    unsigned int btie = 0xFFFFFFFFu;
+    long long bS = 0, bR = 0;
+    for (int r = tid; r < nk; r += kBlock) {
+      const int prev = r == 0 ? nk - 1 : r - 1;
+      if (!(fwd_dist(sph, prev, r) > 0.0)) continue;
+      long long S = 0, R = 0;
+      int last = r;
+      for (int len = 1; len <= nk - 1; ++len) {
+        S += sq[last];
+        R += WEIGHTED ? (long long)sw[last] : 1ll;
+        const double span = len == 1 ? 0.0 : fwd_dist(sph, r, last);
+        if (!(span < qhi)) break;
+        const int next = last + 1 == nk ? 0 : last + 1;
+        const int cur = last;
+        last = next;
+        if (!(fwd_dist(sph, cur, next) > 0.0)) continue;
+        const double gap = prev == next ? 1.0 : fwd_dist(sph, prev, next);
+        if (!(gap > qlo)) continue;
+        if (len < a.min_in_points) continue;
+        if (DIP && !(S < 0)) continue;
+        const double Rd = (double)R;
+        const double den = Rd * (Wd - Rd);
+        if (!(den > 0.0)) continue;
+        const double Sd = (double)S;
+        const double v = Sd * Sd / den;
+        if (!(v > 0.0)) continue;
+        const unsigned int tie = (unsigned)len * (unsigned)nk + (unsigned)r;
+        if (v > bv || (v == bv && tie < btie)) {
+          bv = v;
+          btie = tie;
+          bS = S;
+          bR = R;
+        }
+      }
+    }
+    const unsigned long long vb = (unsigned long long)__double_as_longlong(bv);
+    if (bv > 0.0) atomicMax(&s_vbits, vb);
+    __syncthreads();
+    if (bv > 0.0 && vb == s_vbits) atomicMin(&s_tie, btie);
+    __syncthreads();
+    if (bv > 0.0 && vb == s_vbits && btie == s_tie) {
+      s_bestS = bS;
+      s_bestR = bR;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float srf = 0.0f;
+      if (s_vbits == 0ull) {
+        a.sr[r_out] = 0.0f;
+        a.depth[r_out] = NAN;
+        a.jstart[r_out] = -1;
+        a.kwidth[r_out] = -1;
+      } else {
+        const int len = (int)(s_tie / (unsigned)nk);
+        const int r = (int)(s_tie - (unsigned)len * (unsigned)nk);
+        const double scale = WEIGHTED ? ldexp(1.0, cd.ew - cd.es) : ldexp(1.0, -cd.es);
+        const double v = __longlong_as_double((long long)s_vbits);
+        const double Rd = (double)s_bestR;
+        const double den = Rd * (Wd - Rd);
+        srf = (float)(sqrt(v) * scale);
+        a.sr[r_out] = srf;
+        a.depth[r_out] = (float)(-(double)s_bestS * Wd / den * scale);
+        a.jstart[r_out] = sidx[r];
+        a.kwidth[r_out] = sidx[(r + len - 1) % nk];
+      }
+      const unsigned long long ckey = ((unsigned long long)__float_as_uint(srf) << 32) |
+                                      (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+      __hip_atomic_fetch_max(a.best_key + c, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    }  // valid curve
+    __syncthreads();
+  }
+}
+
+template <bool W, bool D>
+const void *unbinned_fn() {
+  return reinterpret_cast<const void *>(&unbinned_kernel<W, D>);
+}
+
+const void *pick_unbinned(bool weighted, bool dip) {
+  if (weighted) return dip ? unbinned_fn<true, true>() : unbinned_fn<true, false>();
+  return dip ? unbinned_fn<false, true>() : unbinned_fn<false, false>();
+}
+
 __global__ void fill_kernel(unsigned long long *counter, unsigned long long *keys, int32_t nkeys) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && counter) *counter = 0ull;
+  if (i < kMaxParts && counter) counter[i] = 0ull;
   if (i < nkeys) keys[i] = 0ull;
 }
 
@@ -1008,8 +1502,46 @@ int launch_window(const WindowArgs &a, int grid, void *stream) {
   return (int)hipGetLastError();
 }
 
+int launch_variability(const VarArgs &a, void *stream) {
+  if (a.ncurves <= 0 || a.nchips <= 0) return 0;
+  hipStream_t s = (hipStream_t)stream;
+  const int per = kBlock / 64;
+  hipLaunchKernelGGL(var_rms_kernel, dim3((a.ncurves + per - 1) / per), dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  const int64_t tasks = (int64_t)a.nchips * a.nmagbins;
+  hipLaunchKernelGGL(var_clip_kernel, dim3((unsigned)((tasks + per - 1) / per)), dim3(kBlock), 0,
+                     s, a);
+  return (int)hipGetLastError();
+}
+
 int window_blocks_per_cu(int lds_bytes, int *blocks) {
   const void *fn = reinterpret_cast<const void *>(&window_kernel);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
+}
+
+int unbinned_lds_bytes(int n, bool weighted) {
+  const int N = n < 1 ? 1 : n;
+  const int M = pow2_at_least(N);
+  return 8 * N + 8 * N + 4 * N + 4 * N + 4 * N + 4 * (M + 1) + (weighted ? 4 * N : 0);
+}
+
+int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream) {
+  if (a.nitems <= 0) return 0;
+  const void *fn = pick_unbinned(weighted, dip_only);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, a.hist_bytes);
+  if (e != hipSuccess) return (int)e;
+  void *args[] = {const_cast<SearchArgs *>(&a)};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)a.hist_bytes,
+                      (hipStream_t)stream);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipGetLastError();
+}
+
+int unbinned_blocks_per_cu(bool weighted, bool dip_only, int lds_bytes, int *blocks) {
+  const void *fn = pick_unbinned(weighted, dip_only);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return (int)e;
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);

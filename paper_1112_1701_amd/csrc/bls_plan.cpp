@@ -85,7 +85,7 @@ int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t 
 }
 
 int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
-                   std::vector<CurveShape> &shapes, std::string &err) {
+                   std::vector<CurveShape> &shapes, std::string &err, bool binned) {
   char msg[256];
   if (b.ncurves < 1 || b.n_off == nullptr || b.times == nullptr || b.flux == nullptr ||
       b.periods == nullptr) {
@@ -143,9 +143,25 @@ int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_da
     }
     s.nperiods = (int32_t)np;
     total_results += np;
-    s.nbins = b.nbins ? b.nbins[c] : b.nbins_all;
     const double qmin = b.qmin ? b.qmin[c] : b.qmin_all;
     const double qmax = b.qmax ? b.qmax[c] : b.qmax_all;
+    if (!binned) {
+      s.nbins = 0;
+      s.kmin = s.kmax = 0;
+      if (!(qmin > 0.0) || !(qmax < 1.0) || !(qmin <= qmax)) {
+        snprintf(msg, sizeof msg, "curve %d: bad duty-cycle range [%g, %g]", c, qmin, qmax);
+        err = msg;
+        return BLS_ERR_INVALID_ARG;
+      }
+      if (s.n > kUnbinnedMaxPoints) {
+        snprintf(msg, sizeof msg, "curve %d has %lld points (the unbinned search takes at most %d)",
+                 c, (long long)s.n, kUnbinnedMaxPoints);
+        err = msg;
+        return BLS_ERR_CAPACITY;
+      }
+      continue;
+    }
+    s.nbins = b.nbins ? b.nbins[c] : b.nbins_all;
     if (s.nbins < 2) {
       snprintf(msg, sizeof msg, "curve %d: nbins %d < 2", c, s.nbins);
       err = msg;
@@ -222,6 +238,43 @@ int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_da
   return BLS_OK;
 }
 
+// Segments of the batch, grouped by work partition.  Curves go to the
+// partitions round-robin in descending cost, so each partition (one per XCD:
+// the device dispatches workgroups to its XCDs round-robin) gets a similar
+// share, largest first, and every curve's period tiles stay in one XCD's L2:
+// the curve is fetched by one L2 and adjacent tiles' partial result lines
+// merge there before write-back.
+void layout_partitions(bls_plan *p, const std::vector<double> &cost,
+                       const std::vector<int64_t> &items_of, PlannedBatch &out) {
+  const int nc = (int)cost.size();
+  p->order.resize(nc);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  std::stable_sort(p->order.begin(), p->order.end(),
+                   [&](int a, int b) { return cost[a] > cost[b]; });
+  // Few curves (fewer than two per XCD) share one partition: splitting them
+  // would only make most workgroups probe empty partitions first.
+  const int np =
+      (p->num_cus > 0 && p->num_cus % kMaxParts == 0 && nc >= 2 * kMaxParts) ? kMaxParts : 1;
+  int64_t items = 0;
+  int s = 0;
+  for (int x = 0; x < np; ++x) {
+    out.part_begin[x] = items;
+    for (int k = x; k < nc; k += np) {
+      const int c = p->order[k];
+      p->h_seg_start[s] = items;
+      p->h_seg_curve[s] = c;
+      p->h_seg_tile0[s] = 0;
+      items += items_of[c];
+      ++s;
+    }
+  }
+  for (int x = np; x <= kMaxParts; ++x) out.part_begin[x] = items;
+  p->h_seg_start[nc] = items;
+  out.nparts = np;
+  out.nseg = nc;
+  out.nitems = items;
+}
+
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out) {
   const int nc = (int)shapes.size();
@@ -270,23 +323,15 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
                          " bytes of LDS, more than a workgroup has");
   }
 
-  // Largest items first, so the persistent grid drains evenly.
-  p->order.resize(nc);
-  std::iota(p->order.begin(), p->order.end(), 0);
-  std::stable_sort(p->order.begin(), p->order.end(),
-                   [&](int a, int b) { return item_cost[a] > item_cost[b]; });
-  int64_t items = 0;
-  for (int s = 0; s < nc; ++s) {
-    const int c = p->order[s];
+  // Largest items first within each XCD partition, so the persistent grid
+  // drains evenly.
+  std::vector<int64_t> items_of(nc);
+  for (int c = 0; c < nc; ++c) {
     const CurveDesc &d = p->h_curves[c];
-    p->h_seg_start[s] = items;
-    p->h_seg_curve[s] = c;
-    p->h_seg_tile0[s] = 0;
-    items += (d.nperiods + d.tile - 1) / d.tile;
+    items_of[c] = (d.nperiods + d.tile - 1) / d.tile;
   }
-  p->h_seg_start[nc] = items;
-  out.nseg = nc;
-  out.nitems = items;
+  layout_partitions(p, item_cost, items_of, out);
+  const int64_t items = out.nitems;
   out.hist_bytes = hist_bytes;
 
   int per_cu = 0;
@@ -302,7 +347,7 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
 
 int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
                    const double *w, const double *periods, float *sr, float *depth, int32_t *js,
-                   int32_t *ks, int64_t *best, bool timed) {
+                   int32_t *ks, int64_t *best, bool timed, bool unbinned) {
   hipStream_t st = p->stream;
   hipError_t e;
   const int nc = pb.ncurves;
@@ -355,12 +400,17 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
   sa.kwidth = ks;
   sa.best_key = keys;
   sa.hist_bytes = pb.hist_bytes;
+  sa.ucap = pb.ucap;
+  sa.nparts = pb.nparts;
+  sa.pad_parts = 0;
+  for (int x = 0; x <= kMaxParts; ++x) sa.part_begin[x] = pb.part_begin[x];
   if (timed) {
     e = hipEventRecord(p->ev_search0, st);
     if (e != hipSuccess) return hip_error(p, e, "event record");
   }
-  e = (hipError_t)launch_search(sa, pb.weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0, pb.grid,
-                                st);
+  const bool dip = (p->cfg.flags & BLS_DIP_ONLY) != 0;
+  e = unbinned ? (hipError_t)launch_unbinned(sa, pb.weighted, dip, pb.grid, st)
+               : (hipError_t)launch_search(sa, pb.weighted, dip, pb.grid, st);
   if (e != hipSuccess) return hip_error(p, e, "launch search");
   if (timed) {
     e = hipEventRecord(p->ev_search1, st);
@@ -642,7 +692,8 @@ int bls_plan_destroy(bls_plan *p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   drop_graph(p);
   for (void *d : {(void *)p->d_detect_desc, (void *)p->d_detect_out,
-                  (void *)p->d_window_desc, (void *)p->d_window_flag})
+                  (void *)p->d_window_desc, (void *)p->d_window_flag,
+                  (void *)p->d_var_noff, (void *)p->d_var_alive, (void *)p->d_var_chip})
     free_dev(d);
   for (void *d : {(void *)p->d_curves, (void *)p->d_seg_start, (void *)p->d_seg_curve,
                   (void *)p->d_seg_tile0, (void *)p->d_dt, (void *)p->d_q, (void *)p->d_qw,
@@ -756,6 +807,76 @@ int bls_search_device(bls_plan *p, const bls_batch *b, const bls_device_results 
     if (st != BLS_OK) return st;
     p->search_timed = true;
   }
+  if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+  fill_stats(p, pb, false);
+  return BLS_OK;
+}
+
+int bls_search_unbinned_device(bls_plan *p, const bls_batch *b, const bls_unbinned_results *o) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!b || !o || !o->sr || !o->depth || !o->first_point || !o->last_point || !o->best_index)
+    return set_error(p, BLS_ERR_INVALID_ARG, "batch and every device result array are required");
+  p->last_error.clear();
+  std::string err;
+  int st = validate_batch(p->cfg, *b, false, p->shapes, err, false);
+  if (st != BLS_OK) return set_error(p, st, err);
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  const bool weighted = b->weights != nullptr;
+  const int nc = b->ncurves;
+  PlannedBatch pb;
+  pb.ncurves = nc;
+  pb.weighted = weighted;
+  std::vector<double> cost(nc);
+  int ucap = 1;
+  for (int c = 0; c < nc; ++c) {
+    const CurveShape &s = p->shapes[c];
+    CurveDesc &d = p->h_curves[c];
+    memset(&d, 0, sizeof d);
+    d.n_off = s.n_off;
+    d.n = s.n;
+    d.p_off = s.p_off;
+    d.r_off = s.r_off;
+    d.nperiods = s.nperiods;
+    d.nbins = 0;
+    const int cb = cbits_of(s.n);
+    d.shift = 64 - cb;
+    d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
+    d.weighted = weighted ? 1 : 0;
+    d.check_periods = (c == 0 || s.p_off != p->shapes[0].p_off) ? 1 : 0;
+    d.tile = 1;
+    d.qlo = b->qmin ? b->qmin[c] : b->qmin_all;
+    d.qhi = b->qmax ? b->qmax[c] : b->qmax_all;
+    ucap = std::max<int>(ucap, (int)s.n);
+    // a start's run covers about qhi * n points
+    cost[c] = (double)s.n * (1.0 + d.qhi * (double)s.n);
+    pb.total_points += s.n;
+    pb.total_results += s.nperiods;
+    pb.trial_points += (double)s.n * (double)s.nperiods;
+    pb.box_evals += (double)s.n * d.qhi * (double)s.n * (double)s.nperiods;
+  }
+  std::vector<int64_t> items_of(nc);
+  for (int c = 0; c < nc; ++c) items_of[c] = p->h_curves[c].nperiods;
+  layout_partitions(p, cost, items_of, pb);
+  const int64_t items = pb.nitems;
+  pb.ucap = ucap;
+  pb.hist_bytes = unbinned_lds_bytes(ucap, weighted);
+  if (pb.hist_bytes > p->max_lds - 2048)
+    return set_error(p, BLS_ERR_CAPACITY, "curve too long for the unbinned search's LDS");
+  int per_cu = 0;
+  if ((e = (hipError_t)unbinned_blocks_per_cu(weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0,
+                                              pb.hist_bytes, &per_cu)) != hipSuccess)
+    return hip_error(p, e, "occupancy query");
+  if (per_cu < 1) return set_error(p, BLS_ERR_CAPACITY, "unbinned kernel does not fit a CU");
+  pb.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)p->num_cus * per_cu));
+  // the pinned descriptors were rewritten: a captured search graph is stale
+  drop_graph(p);
+  p->last = pb;
+  if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
+  st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
+                      o->first_point, o->last_point, o->best_index, true, true);
+  if (st != BLS_OK) return st;
+  p->search_timed = true;
   if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   fill_stats(p, pb, false);
   return BLS_OK;
@@ -891,13 +1012,32 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
   a.min_eclipses = min_eclipses;
   a.duration = duration;
   a.overflow = p->d_window_flag;
+  if ((e = hipEventRecord(p->ev_search0, s)) != hipSuccess) return hip_error(p, e, "event");
   if ((e = (hipError_t)launch_window(a, (int)grid, s))) return hip_error(p, e, "launch window");
+  if ((e = hipEventRecord(p->ev_search1, s)) != hipSuccess) return hip_error(p, e, "event");
   unsigned int flag = 0;
   if ((e = hipMemcpyAsync(wd.data(), p->d_window_desc, sizeof(WindowDesc) * nc,
                           hipMemcpyDeviceToHost, s)) ||
       (e = hipMemcpyAsync(&flag, p->d_window_flag, sizeof flag, hipMemcpyDeviceToHost, s)) ||
       (e = hipStreamSynchronize(s)))
     return hip_error(p, e, "eclipse window");
+  {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1);
+    p->stats = bls_call_stats{};
+    p->stats.search_ms = p->stats.total_ms = ms;
+    double pp = 0.0, dec = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      pp += (double)wd[c].n * (double)wd[c].nperiods;
+      dec += (double)wd[c].nperiods * (double)nphase;
+    }
+    p->stats.trial_points = pp;
+    p->stats.box_evals = dec;
+    p->stats.work_items = items;
+    p->stats.grid = (int32_t)grid;
+    p->stats.block = kBlock;
+    p->stats.lds_bytes = lds;
+  }
   for (int c = 0; c < nc; ++c) {
     if (wd[c].status != kCurveOk) {
       snprintf(msg, sizeof msg, "cadence %d: %s", c,
@@ -909,6 +1049,98 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
   }
   if (flag)
     return set_error(p, BLS_ERR_CAPACITY, "a cadence spans more than 2^29 cycles of a period");
+  return BLS_OK;
+}
+
+int bls_variability_device(bls_plan *p, const bls_batch *b, const bls_variability_config *cfg,
+                           const bls_variability_results *o) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  if (!b || !cfg || !o || !b->n_off || !b->flux || !cfg->chip_off || !cfg->mag || !o->rms ||
+      !o->bin || !o->flag || !o->bin_mean || !o->bin_std || !o->bin_count)
+    return set_error(p, BLS_ERR_INVALID_ARG,
+                     "need batch (n_off, flux), config (chip_off, mag) and every result array");
+  const int nc = b->ncurves, nk = cfg->nchips;
+  if (nc < 1 || nk < 1 || cfg->nmagbins < 1 || !(cfg->width > 0.0) || !isfinite(cfg->width) ||
+      !isfinite(cfg->origin) || !(cfg->clip_sigma > 0.0) || !(cfg->flag_sigma >= 0.0) ||
+      cfg->max_iter < 0 || cfg->min_stars < 1)
+    return set_error(p, BLS_ERR_INVALID_ARG,
+                     "need ncurves, nchips, nmagbins >= 1, finite origin, width > 0, "
+                     "clip_sigma > 0, flag_sigma >= 0, max_iter >= 0, min_stars >= 1");
+  if (nc > p->cfg.max_curves || cfg->nmagbins > kVarMaxBins || cfg->max_iter > kVarMaxIter)
+    return set_error(p, BLS_ERR_CAPACITY,
+                     "more curves than max_curves, nmagbins > 4096 or max_iter > 64");
+  if (b->n_off[0] != 0 || cfg->chip_off[0] != 0 || cfg->chip_off[nk] != nc)
+    return set_error(p, BLS_ERR_INVALID_ARG, "n_off[0], chip_off[0] must be 0; "
+                                             "chip_off[nchips] must equal ncurves");
+  for (int c = 0; c < nc; ++c)
+    if (b->n_off[c + 1] < b->n_off[c])
+      return set_error(p, BLS_ERR_INVALID_ARG, "n_off must be non-decreasing");
+  for (int k = 0; k < nk; ++k)
+    if (cfg->chip_off[k + 1] < cfg->chip_off[k])
+      return set_error(p, BLS_ERR_INVALID_ARG, "chip_off must be non-decreasing");
+  if (b->n_off[nc] > p->cfg.max_points)
+    return set_error(p, BLS_ERR_CAPACITY, "points exceed the plan's max_points");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  if (!p->d_var_noff) {
+    const size_t mc = (size_t)p->cfg.max_curves;
+    if ((e = device_alloc((void **)&p->d_var_noff, 8 * (mc + 1))) ||
+        (e = device_alloc((void **)&p->d_var_alive, mc))) {
+      free_dev(p->d_var_noff);
+      free_dev(p->d_var_alive);
+      p->d_var_noff = nullptr;
+      p->d_var_alive = nullptr;
+      return hip_error(p, e, "allocate variability scratch");
+    }
+  }
+  if (nk > p->var_chip_cap) {
+    free_dev(p->d_var_chip);
+    p->d_var_chip = nullptr;
+    p->var_chip_cap = 0;
+    if ((e = device_alloc((void **)&p->d_var_chip, 8 * ((size_t)nk + 1))))
+      return hip_error(p, e, "allocate chip offsets");
+    p->var_chip_cap = nk;
+  }
+  hipStream_t s = p->stream;
+  if ((e = hipMemcpyAsync(p->d_var_noff, b->n_off, 8 * ((size_t)nc + 1), hipMemcpyHostToDevice,
+                          s)) ||
+      (e = hipMemcpyAsync(p->d_var_chip, cfg->chip_off, 8 * ((size_t)nk + 1),
+                          hipMemcpyHostToDevice, s)))
+    return hip_error(p, e, "upload offsets");
+  VarArgs a;
+  memset(&a, 0, sizeof a);
+  a.ncurves = nc;
+  a.nchips = nk;
+  a.nmagbins = cfg->nmagbins;
+  a.max_iter = cfg->max_iter;
+  a.min_stars = cfg->min_stars;
+  a.n_off = p->d_var_noff;
+  a.chip_off = p->d_var_chip;
+  a.x = b->flux;
+  a.w = b->weights;
+  a.mag = cfg->mag;
+  a.origin = cfg->origin;
+  a.width = cfg->width;
+  a.clip_sigma = cfg->clip_sigma;
+  a.flag_sigma = cfg->flag_sigma;
+  a.rms = o->rms;
+  a.bin = o->bin;
+  a.flag = o->flag;
+  a.bin_mean = o->bin_mean;
+  a.bin_std = o->bin_std;
+  a.bin_count = o->bin_count;
+  a.alive = p->d_var_alive;
+  if ((e = hipEventRecord(p->ev_search0, s)) != hipSuccess) return hip_error(p, e, "event");
+  if ((e = (hipError_t)launch_variability(a, s))) return hip_error(p, e, "launch variability");
+  if ((e = hipEventRecord(p->ev_search1, s)) != hipSuccess) return hip_error(p, e, "event");
+  if ((e = hipStreamSynchronize(s))) return hip_error(p, e, "variability");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1);
+  p->stats = bls_call_stats{};
+  p->stats.search_ms = p->stats.total_ms = ms;
+  p->stats.trial_points = (double)b->n_off[nc];
+  p->stats.box_evals = (double)nc;
+  p->stats.block = kBlock;
   return BLS_OK;
 }
 

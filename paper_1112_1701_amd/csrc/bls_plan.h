@@ -32,6 +32,9 @@ struct PlannedBatch {
   int32_t grid = 0;
   double trial_points = 0.0;
   double box_evals = 0.0;
+  int32_t ucap = 0;         // unbinned search: largest curve (points)
+  int32_t nparts = 1;       // work partitions (XCDs)
+  int64_t part_begin[bls::kMaxParts + 1] = {};
 };
 
 // Per-curve shape after validation (host only).
@@ -75,6 +78,12 @@ struct bls_plan {
   bls::WindowDesc *d_window_desc = nullptr;
   unsigned int *d_window_flag = nullptr;
 
+  // variability pre-search scratch (allocated on first use, grown as needed)
+  int64_t *d_var_noff = nullptr;      // [max_curves + 1]
+  uint8_t *d_var_alive = nullptr;     // [max_curves]
+  int64_t *d_var_chip = nullptr;      // [var_chip_cap + 1]
+  int64_t var_chip_cap = 0;
+
   // pinned host descriptors
   bls::CurveDesc *h_curves = nullptr;
   int64_t *h_seg_start = nullptr;
@@ -104,18 +113,27 @@ struct bls_plan {
 namespace bls {
 
 // Validation of a batch description and its parameters (host only; no
-// device access).  With check_data, also the host data arrays.
+// device access).  With check_data, also the host data arrays.  Without
+// binned, nbins is ignored and each curve's duty-cycle range is checked as
+// phase limits (0 < qmin <= qmax < 1) with at most kUnbinnedMaxPoints points.
 int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
-                   std::vector<CurveShape> &shapes, std::string &err);
+                   std::vector<CurveShape> &shapes, std::string &err, bool binned = true);
+
+// Segments grouped into work partitions (one per XCD), curves assigned
+// round-robin in descending cost; items_of[c] = work items of curve c.
+void layout_partitions(bls_plan *p, const std::vector<double> &cost,
+                       const std::vector<int64_t> &items_of, PlannedBatch &out);
 
 // Fill the pinned descriptors for a validated batch and size the launch.
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out);
 
 // Queue: upload descriptors, clear counters, prep, search, best index.
+// With unbinned, the unbinned kernel replaces the search kernel (js and ks
+// then receive the first and last point of each best box).
 int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
                    const double *w, const double *periods, float *sr, float *depth,
-                   int32_t *js, int32_t *ks, int64_t *best, bool timed);
+                   int32_t *js, int32_t *ks, int64_t *best, bool timed, bool unbinned = false);
 
 int set_error(bls_plan *p, int status, const std::string &msg);
 int hip_error(bls_plan *p, hipError_t e, const char *what);

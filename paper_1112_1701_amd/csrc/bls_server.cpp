@@ -234,6 +234,8 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
   a.kwidth = s->d_ks;
   a.best_key = s->d_keys;
   a.hist_bytes = hist_bytes;
+  a.ucap = 0;
+  single_partition(a);
   const bool dip = (s->cfg.flags & BLS_DIP_ONLY) != 0;
   int per_cu = 1;
   if ((e = (hipError_t)search_blocks_per_cu(tk.weighted, dip, hist_bytes, &per_cu))) return e;

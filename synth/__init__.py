@@ -22,4 +22,5 @@ from .lightcurves import (  # noqa: F401
     small_curve,
     survey_cadence,
     cadence_batch,
+    variability_field,
 )

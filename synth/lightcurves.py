@@ -27,6 +27,11 @@ Workload recipes (sizes per the benchmark configurations):
             clear night a 4.5-h window opening 0.1-0.15 d after the night's
             integer HJD holds exposures every U(15, 25) min; 64 fields share
             100000 log periods 0.1-10 d, 1000 trial epochs, eclipses 0.02 d.
+* field:    one pointing's stars for the variability pre-search: 100000
+            stars on 11 chips, R magnitudes U(14, 20), U{140..300} epochs,
+            noise sqrt(0.003^2 + (0.01 * 10^(0.4 (m - 17)))^2) mag, 3% of
+            stars variable (sinusoid, amplitude U(0.02, 0.3) mag, period
+            log-U(0.1, 10) d); values are magnitudes.
 * serving:  Poisson arrivals; each request N log-U[500, 20000], U{5000..100000}
             periods in 0.2-10 d, U{200..1000} bins, q in [0.01, 0.10], 20%
             with a box.
@@ -339,3 +344,29 @@ def cadence_batch(ncadences: int = 64, nperiods: int = 100000,
                  log_period_grid(pmin, pmax, nperiods), None,
                  np.full(ncadences, 2, np.int32), np.full(ncadences, 0.1),
                  np.full(ncadences, 0.1))
+
+
+def variability_field(nstars: int = 100000, nchips: int = 11,
+                      seed: int = _BASE_SEED + 7, var_frac: float = 0.03):
+    """Stars of one pointing (magnitudes over time) for the pre-search.
+
+    Returns (Batch of magnitude light curves, mag [nstars], chip_off
+    [nchips + 1], variable [nstars] bool).
+    """
+    rng = np.random.default_rng(seed)
+    mag = rng.uniform(14.0, 20.0, nstars)
+    n = rng.integers(140, 301, nstars)
+    n_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    sig = np.sqrt(0.003 ** 2 + (0.01 * 10 ** (0.4 * (mag - 17.0))) ** 2)
+    var = rng.uniform(size=nstars) < var_frac
+    t = T_START + rng.uniform(0.0, 90.0, n_off[-1])
+    star = np.repeat(np.arange(nstars), n)
+    x = mag[star] + sig[star] * rng.standard_normal(n_off[-1])
+    amp = rng.uniform(0.02, 0.3, nstars) * var
+    per = np.exp(rng.uniform(np.log(0.1), np.log(10.0), nstars))
+    x = x + amp[star] * np.sin(2 * np.pi * t / per[star])
+    chip_off = np.linspace(0, nstars, nchips + 1).round().astype(np.int64)
+    b = Batch(t, x, None, n_off, np.array([1.0]), None,
+              np.full(nstars, 2, np.int32), np.full(nstars, 0.1),
+              np.full(nstars, 0.1))
+    return b, mag, chip_off, var

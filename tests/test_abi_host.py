@@ -45,7 +45,10 @@ def test_struct_layouts_match_c():
                "bls_results": L.BlsResults,
                "bls_device_results": L.BlsDeviceResults,
                "bls_call_stats": L.BlsCallStats,
-               "bls_detection": L.BlsDetection}
+               "bls_detection": L.BlsDetection,
+               "bls_variability_config": L.BlsVariabilityConfig,
+               "bls_variability_results": L.BlsVariabilityResults,
+               "bls_unbinned_results": L.BlsUnbinnedResults}
     text = open(HEADER).read()
     for opt, cls in (("bls_request", L.BlsRequest),
                      ("bls_result", L.BlsResult),
