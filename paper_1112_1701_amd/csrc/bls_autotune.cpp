@@ -154,11 +154,14 @@ double time_candidate(bls_plan *p, std::vector<CurveShape> &shapes, bool weighte
 
 TileChoice tune(bls_plan *p, const Bucket &bk, const CurveShape &rep, bool weighted) {
   TileChoice def = default_tiles(weighted);
-  // Sample: enough items to fill the GPU a few times at the smallest tile.
+  // Sample: enough items for a few dozen per workgroup at the mid-size
+  // tiles, so a candidate is timed in the steady state of the persistent
+  // grid rather than its ramp-up and tail (at 1024 periods per curve the
+  // 8- and 12-period tiles differed by less than the run-to-run noise).
   const int64_t n = std::max<int64_t>(2, std::min<int64_t>(rep.n, p->cfg.max_points / 4));
   int ncurves = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(
       64, p->cfg.max_curves), p->cfg.max_points / n));
-  const int m = 1024;
+  const int m = 8192;
   if ((int64_t)ncurves * m > p->cfg.max_periods) ncurves = (int)std::max<int64_t>(1, p->cfg.max_periods / m);
   if (ncurves < 1 || (int64_t)ncurves * m > p->cfg.max_periods) return def;
 
@@ -196,7 +199,7 @@ TileChoice tune(bls_plan *p, const Bucket &bk, const CurveShape &rep, bool weigh
     const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int T : cands) {
       if (T > kTileMax || T * per_period > p->max_lds - 1024) break;
-      const double ms = time_candidate(p, shapes, weighted, T, per, sr, depth, js, ks, keys, 2);
+      const double ms = time_candidate(p, shapes, weighted, T, per, sr, depth, js, ks, keys, 3);
       if (ms <= 0.0) continue;
       const double rate = 1.0 / ms;  // same work for every candidate
       if (rate > best_rate * 1.02) {  // prefer the smaller tile on near-ties

@@ -472,6 +472,48 @@ __device__ inline long long next_item(const SearchArgs &a, unsigned &done_mask) 
   return -1;
 }
 
+// A claimed work item and its place: curve and tile (period, for the
+// unbinned search) within the curve.
+struct ItemRef {
+  long long item;
+  int curve;
+  int tile;
+};
+
+// The segment of the last claimed item, kept in thread 0's registers:
+// items of a partition are claimed in increasing order, so the next one
+// usually falls in the same segment and needs no memory access to place.
+struct SegCache {
+  long long lo, hi;  // items [lo, hi) of the segment
+  int curve, tile0;
+};
+
+// Claim the next item and place it (thread 0 only).
+__device__ inline ItemRef claim_item(const SearchArgs &a, unsigned &done_mask, SegCache &sc) {
+  ItemRef r;
+  r.item = next_item(a, done_mask);
+  r.curve = 0;
+  r.tile = 0;
+  if (r.item < 0) return r;
+  if (!(r.item >= sc.lo && r.item < sc.hi)) {
+    int lo = 0, hi = a.nseg - 1;  // last s with seg_start[s] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.seg_start[mid] <= r.item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    sc.lo = a.seg_start[lo];
+    sc.hi = a.seg_start[lo + 1];
+    sc.curve = a.seg_curve[lo];
+    sc.tile0 = a.seg_tile0[lo];
+  }
+  r.curve = sc.curve;
+  r.tile = sc.tile0 + (int)(r.item - sc.lo);
+  return r;
+}
+
 template <bool WEIGHTED, bool DIP>
 __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
@@ -484,24 +526,18 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
 
   const int tid = threadIdx.x;
   constexpr int wpb = WEIGHTED ? 2 : 1;
+  // Thread 0 claims each item one step ahead, while the workgroup works on
+  // the current one, so the claim's atomic and lookups are off the path.
   unsigned done_mask = 0u;
+  SegCache sc = {0, 0, 0, 0};
+  ItemRef nx = {-1, 0, 0};
+  if (tid == 0) nx = claim_item(a, done_mask, sc);
 
   for (;;) {
     if (tid == 0) {
-      const long long it = next_item(a, done_mask);
-      s_item = it;
-      if (it >= 0) {
-        int lo = 0, hi = a.nseg - 1;  // last s with seg_start[s] <= it
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (a.seg_start[mid] <= it)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        s_curve = a.seg_curve[lo];
-        s_tile = a.seg_tile0[lo] + (int)(it - a.seg_start[lo]);
-      }
+      s_item = nx.item;
+      s_curve = nx.curve;
+      s_tile = nx.tile;
     }
     __syncthreads();
     if (s_item < 0) break;
@@ -509,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const int c = __builtin_amdgcn_readfirstlane(s_curve);
     const int tile = __builtin_amdgcn_readfirstlane(s_tile);
     __syncthreads();  // everyone has read the item before thread 0 takes the next
+    if (tid == 0) nx = claim_item(a, done_mask, sc);
 
     const CurveDesc cd = a.curves[c];
     const int p0 = tile * cd.tile;
@@ -874,14 +911,17 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
   const double nbd = (double)nb;
   const unsigned nbm1 = (unsigned)(nb - 1);
 
+  // A workgroup's items increase, so its cadence only moves forward: keep
+  // the current one and the first item of the next.
+  int cur = 0;
+  int64_t next0 = a.ncurves > 1 ? a.desc[1].item0 : a.nitems;
+  WindowDesc wd = a.desc[0];
   for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-    int lo = 0, hi = a.ncurves - 1;          // cadence of this item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.desc[mid].item0 <= item) lo = mid;
-      else hi = mid - 1;
+    if (item >= next0) {
+      while (cur + 1 < a.ncurves && a.desc[cur + 1].item0 <= item) ++cur;
+      wd = a.desc[cur];
+      next0 = cur + 1 < a.ncurves ? a.desc[cur + 1].item0 : a.nitems;
     }
-    const WindowDesc wd = a.desc[lo];
     const int p0 = (int)(item - wd.item0) * a.tile;
     const int np = min(a.tile, wd.nperiods - p0);
     int32_t *out = a.observed + wd.r_off + p0;
@@ -1198,28 +1238,21 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   int *sw = cnt + Mc + 1;   // weighted only
 
   unsigned done_mask = 0u;
+  SegCache sc = {0, 0, 0, 0};
+  ItemRef nx = {-1, 0, 0};
+  if (tid == 0) nx = claim_item(a, done_mask, sc);  // one item ahead
   for (;;) {
     if (tid == 0) {
-      const long long it = next_item(a, done_mask);
-      s_item = it;
-      if (it >= 0) {
-        int lo = 0, hi = a.nseg - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (a.seg_start[mid] <= it)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        s_curve = a.seg_curve[lo];
-        s_per = (int)(it - a.seg_start[lo]);
-      }
+      s_item = nx.item;
+      s_curve = nx.curve;
+      s_per = nx.tile;
     }
     __syncthreads();
     if (s_item < 0) break;
     const int c = __builtin_amdgcn_readfirstlane(s_curve);
     const int p = __builtin_amdgcn_readfirstlane(s_per);
     __syncthreads();
+    if (tid == 0) nx = claim_item(a, done_mask, sc);
 
     const CurveDesc cd = a.curves[c];
     const int64_t r_out = cd.r_off + p;
