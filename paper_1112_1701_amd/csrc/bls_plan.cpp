@@ -304,7 +304,9 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
     d.weighted = weighted ? 1 : 0;
     // each distinct period range is checked once (a shared grid by curve 0)
     d.check_periods = (c == 0 || s.p_off != shapes[0].p_off) ? 1 : 0;
-    const int per_period = (s.nbins + s.kmax - 1) * 8 * wpb;
+    // bins, then the clamp word / wrap-around copy (at least one word), as
+    // the kernel lays them out
+    const int per_period = (s.nbins + std::max(s.kmax - 1, 1)) * 8 * wpb;
     int T = std::max(1, tc.lds_budget / per_period);
     T = std::min(T, std::min(tc.tile_cap, kTileMax));
     T = std::min(T, s.nperiods);

@@ -338,3 +338,21 @@ def test_detection_statistics(bls):
         assert abs(g["sde"] - oe["sde"]) <= 1e-5 * oe["sde"]
         assert g["peak_index"][0] in np.flatnonzero(
             oo.sr >= (1 - 1e-5) * oo.sr.max())
+
+
+def test_single_bin_boxes(bls, plan):
+    """kmax = 1 (20 bins, q up to 0.05): each period's histogram is its bins
+    plus one clamp word, so the LDS tile must hold nbins + 1 words per
+    period; every period of a full tile is checked."""
+    b = synth.uniform_batch(6, 700, 400, 20, seed=91, inj_prob=0.5)
+    _say("single-bin boxes", b.ncurves, b.periods.size)
+    assert bls.bls_width_range(20, 0.01, 0.05) == (1, 1)
+    res = bls.bls_search_batch(plan, b.n_off, b.t, b.x, None, b.periods,
+                               None, 20, 0.01, 0.05)
+    m = b.periods.size
+    for c in range(b.ncurves):
+        lc = b.curve(c)
+        lc.qmin, lc.qmax = 0.01, 0.05
+        g = {k: (v[c * m:(c + 1) * m] if k != "best_index" else v[c])
+             for k, v in res.items()}
+        check_curve(lc, g, _orc(lc), label="kmax1-%d" % c)
