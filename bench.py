@@ -508,6 +508,57 @@ def suite_unbinned(args, bls):
             "cpu_baseline": cpu}
 
 
+def suite_detect(args, bls):
+    """Detection statistics of the uniform batch's 4096 periodograms."""
+    import torch
+
+    import synth
+    log("suite detect")
+    b = synth.config2(4096)
+    db = DeviceBatch(b)
+    with bls.Plan(**db.cap) as p:
+        db.call(bls, p.handle)
+        bls.bls_synchronize(p.handle)
+        kms = []
+        for r in range(args.suite_steps + 1):
+            det = bls.bls_detect_device(p.handle, b.n_off, db.per, None, 300,
+                                        0.01, 0.1, db.outs[0], max_peaks=8,
+                                        window=0.01, sde_threshold=7.0)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+    k_ms = _median(kms[1:])
+    m = float(b.ncurves) * b.periods.size
+    # one pass for the mean, one for the deviation and maximum, one per peak
+    nbytes = 4.0 * m * (2 + 8) + 8.0 * b.periods.size * 8
+    achieved = nbytes / (k_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+
+        import oracle
+        sr = db.outs[0].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        ncur = 0
+        for c in range(b.ncurves):
+            oracle.detect(sr[c * b.periods.size:(c + 1) * b.periods.size],
+                          b.periods, max_peaks=8, window=0.01, threshold=7.0)
+            ncur += 1
+            if time.perf_counter() - t0 > args.cpu_budget / 3:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": ncur * b.periods.size / el, "unit": "periods/s",
+               "cores": 1, "kind": "oracle",
+               "sample": "first %d periodograms" % ncur}
+    return {"workload": "detection statistics: 4096 periodograms x 20000 "
+                        "periods, 8 peaks, window 0.01",
+            "periods": m, "kernel_ms": k_ms,
+            "periods_per_s": m / (k_ms * 1e-3),
+            "candidates": int(sum(d["candidate"] for d in det)),
+            "roofline": {"bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "cpu_baseline": cpu}
+
+
 def suite(args):
     import paper_1112_1701_amd as bls
     import synth
@@ -518,7 +569,7 @@ def suite(args):
             "uniform": synth.config2, "uneven": synth.config3,
             "long": synth.config4}
     extra = {"window": suite_window, "variability": suite_variability,
-             "unbinned": suite_unbinned}
+             "unbinned": suite_unbinned, "detect": suite_detect}
     for name in names:
         if name in extra:
             print(json.dumps(extra[name](args, bls)), flush=True)
@@ -555,7 +606,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--workloads", default="plain,uniform,uneven,long,"
-                    "serving,window,variability,unbinned")
+                    "serving,window,variability,unbinned,detect")
     ap.add_argument("--suite-steps", type=int, default=3)
     ap.add_argument("--rates", default="100,500,1000,2000,5000")
     ap.add_argument("--pool", type=int, default=300)

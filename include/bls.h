@@ -356,10 +356,12 @@ int bls_debug_phase_bins(bls_plan *plan, const double *times, int64_t n,
                          double period, int32_t nbins, int32_t *bins);
 
 /* Timing and shape of the plan's last search, unbinned-search,
- * eclipse-window or variability call (for the last two, search_ms covers
- * their kernels; trial_points is points x periods, resp. points; box_evals
- * is periods x nphase epoch decisions, resp. stars; for the unbinned search
- * box_evals estimates the run steps as sum n * qmax * n * nperiods). */
+ * eclipse-window, variability or detection call.  search_ms covers the
+ * call's kernels.  For the eclipse window trial_points is points x periods
+ * and box_evals periods x nphase epoch decisions; for the variability
+ * pre-search, points and stars; for detection, the periods scanned; for the
+ * unbinned search box_evals estimates the run steps as the sum of
+ * n * qmax * n * nperiods. */
 typedef struct {
     double search_ms;       /* main kernel(s), device time (HIP events)     */
     double total_ms;        /* whole call as queued on the stream           */

@@ -378,79 +378,78 @@ __device__ __forceinline__ void scan_task_unit(const float2 *h, int kmin, int km
   }
 }
 
-// One lane task, weighted curves: running sums of weight R, signal S and
-// count C (ha: the period's (R, S) bins from start j, hc: their counts in
-// .x); screen S^2 >= theta R (W - R).
+// Exact test of one weighted box that passed the screen.  Its point count,
+// needed only for the validity test, is summed here from the count bins
+// (hc) rather than carried through the scan; without need_counts (no box
+// can hold every point and one point makes a box valid) R (W - R) > 0
+// alone decides validity.
 template <bool DIP>
-__device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float2 *hc, int kmin,
-                                                   int kmax, float Wf, float thr, float nmax1,
-                                                   float mipf, float &bn, float &bd, int &bm) {
-  float R = 0.0f, S = 0.0f, C = 0.0f;
-  int m = 0;
-  for (; m < kmin - 1; ++m) {
-    const float2 e = ha[m];
-    R += e.x;
-    S += e.y;
-    C += hc[m].x;
+__device__ __forceinline__ void consider_w(float R, float S, float d, int m, const float2 *hc,
+                                           bool need_counts, float nmax1, float mipf, float &bn,
+                                           float &bd, int &bm) {
+  const float num = S * S;
+  const float den = R * d;
+  bool ok = (num * bd > bn * den) & (den > 0.0f);
+  if (DIP) ok = ok & (S < 0.0f);
+  if (ok && need_counts) {
+    float C = 0.0f;
+    for (int i = 0; i <= m; ++i) C += hc[i].x;
+    ok = (C <= nmax1) & (C >= mipf);
   }
-  bn = 0.0f;
-  bd = 1.0f;
-  bm = -1;
-  for (; m < kmax; ++m) {
-    const float2 e = ha[m];
-    R += e.x;
-    S += e.y;
-    C += hc[m].x;
-    const float d = Wf - R;
-    if (S * S >= thr * (R * d)) consider<true, DIP, false>(R, S, C, d, m, nmax1, mipf, bn, bd, bm);
+  if (ok) {
+    bn = num;
+    bd = den;
+    bm = m;
   }
 }
 
-// One lane task, weighted curves, when no box can hold every point (the
-// period has more non-empty bins than the widest box) and one point makes a
-// box valid: a box with S != 0 then has points inside and outside, so only
-// R (W - R) > 0 is checked and the counts are not needed.
+// One lane task, weighted curves: as for unit weights, d = W - R is kept by
+// subtraction and u = theta R by fused multiply-add, so the screen
+// S^2 >= u d costs six operations per box (ha: the period's (R, S) bins
+// from start j; hc: their counts in .x, read only for boxes that pass).
 template <bool DIP>
-__device__ __forceinline__ void scan_task_weighted_free(const float2 *h, int kmin, int kmax,
-                                                        float Wf, float thr, float &bn, float &bd,
-                                                        int &bm) {
-  float R = 0.0f, S = 0.0f;
+__device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float2 *hc, int kmin,
+                                                   int kmax, float Wf, float thr, float nmax1,
+                                                   float mipf, bool need_counts, float &bn,
+                                                   float &bd, int &bm) {
+  float d = Wf, S = 0.0f, u = 0.0f;
   int m = 0;
   for (; m < kmin - 1; ++m) {
-    const float2 e = h[m];
-    R += e.x;
+    const float2 e = ha[m];
+    d -= e.x;
     S += e.y;
+    u = fmaf(thr, e.x, u);
   }
   bn = 0.0f;
   bd = 1.0f;
   bm = -1;
   for (; m + 4 <= kmax; m += 4) {
-    const float2 e0 = h[m], e1 = h[m + 1], e2 = h[m + 2], e3 = h[m + 3];
-    const float R0 = R + e0.x, S0 = S + e0.y;
-    const float R1 = R0 + e1.x, S1 = S0 + e1.y;
-    const float R2 = R1 + e2.x, S2 = S1 + e2.y;
-    const float R3 = R2 + e3.x, S3 = S2 + e3.y;
-    const float den0 = R0 * (Wf - R0), den1 = R1 * (Wf - R1);
-    const float den2 = R2 * (Wf - R2), den3 = R3 * (Wf - R3);
-    const bool p0 = S0 * S0 >= thr * den0;
-    const bool p1 = S1 * S1 >= thr * den1;
-    const bool p2 = S2 * S2 >= thr * den2;
-    const bool p3 = S3 * S3 >= thr * den3;
+    const float2 e0 = ha[m], e1 = ha[m + 1], e2 = ha[m + 2], e3 = ha[m + 3];
+    const float d0 = d - e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
+    const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
+    const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
+    const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
+    const bool p0 = S0 * S0 >= u0 * d0;
+    const bool p1 = S1 * S1 >= u1 * d1;
+    const bool p2 = S2 * S2 >= u2 * d2;
+    const bool p3 = S3 * S3 >= u3 * d3;
     if (p0 | p1 | p2 | p3) {
-      if (p0) consider<true, DIP, false>(R0, S0, 0.5f, Wf - R0, m, 1.0f, 0.0f, bn, bd, bm);
-      if (p1) consider<true, DIP, false>(R1, S1, 0.5f, Wf - R1, m + 1, 1.0f, 0.0f, bn, bd, bm);
-      if (p2) consider<true, DIP, false>(R2, S2, 0.5f, Wf - R2, m + 2, 1.0f, 0.0f, bn, bd, bm);
-      if (p3) consider<true, DIP, false>(R3, S3, 0.5f, Wf - R3, m + 3, 1.0f, 0.0f, bn, bd, bm);
+      if (p0) consider_w<DIP>(Wf - d0, S0, d0, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
+      if (p1) consider_w<DIP>(Wf - d1, S1, d1, m + 1, hc, need_counts, nmax1, mipf, bn, bd, bm);
+      if (p2) consider_w<DIP>(Wf - d2, S2, d2, m + 2, hc, need_counts, nmax1, mipf, bn, bd, bm);
+      if (p3) consider_w<DIP>(Wf - d3, S3, d3, m + 3, hc, need_counts, nmax1, mipf, bn, bd, bm);
     }
-    R = R3;
+    d = d3;
     S = S3;
+    u = u3;
   }
   for (; m < kmax; ++m) {
-    const float2 e = h[m];
-    R += e.x;
+    const float2 e = ha[m];
+    d -= e.x;
     S += e.y;
-    const float d = Wf - R;
-    if (S * S >= thr * (R * d)) consider<true, DIP, false>(R, S, 0.5f, d, m, 1.0f, 0.0f, bn, bd, bm);
+    u = fmaf(thr, e.x, u);
+    if (S * S >= u * d)
+      consider_w<DIP>(Wf - d, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
   }
 }
 
@@ -655,10 +654,9 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         int bm;
         if (WEIGHTED) {
           const float2 *ha = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HB * 2) + j;
-          if (mip1 && s_nonempty[t] > kmax)
-            scan_task_weighted_free<DIP>(ha, kmin, kmax, Wf, thr, bn, bd, bm);
-          else
-            scan_task_weighted<DIP>(ha, ha + HB, kmin, kmax, Wf, thr, nmax1, mipf, bn, bd, bm);
+          const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
+          scan_task_weighted<DIP>(ha, ha + HB, kmin, kmax, Wf, thr, nmax1, mipf, need_counts, bn,
+                                  bd, bm);
         } else {
           const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
           if (mip1)
@@ -916,6 +914,13 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
   int cur = 0;
   int64_t next0 = a.ncurves > 1 ? a.desc[1].item0 : a.nitems;
   WindowDesc wd = a.desc[0];
+  // The cadence's times (d = t - t0, kept points only) stay in registers
+  // across the workgroup's items of that cadence when it has at most
+  // kBlock * kWinRegs points; longer cadences are read again per item.
+  constexpr int kWinRegs = 8;
+  double dreg[kWinRegs];
+  bool kreg[kWinRegs];
+  int cached = -1;
   for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
     if (item >= next0) {
       while (cur + 1 < a.ncurves && a.desc[cur + 1].item0 <= item) ++cur;
@@ -942,10 +947,7 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
 
     // Fold: cycle numbers per bin.
     bool over = false;
-    for (int64_t i = tid; i < wd.n; i += kBlock) {
-      const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
-      if (wi == 0.0) continue;
-      const double d = a.t[wd.n_off + i] - wd.t0;
+    auto fold_point = [&](double d) {
       for (int t = 0; t < np; ++t) {
         const double cyc = d * s_f[t];
         const double e = floor(cyc);
@@ -955,6 +957,28 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
         int *w2 = reinterpret_cast<int *>(s_mm + t * nb + b);
         atomicMin(w2, ei);
         atomicMax(w2 + 1, ei);
+      }
+    };
+    if (wd.n <= (int64_t)kBlock * kWinRegs) {
+      if (cached != cur) {
+#pragma unroll
+        for (int r = 0; r < kWinRegs; ++r) {
+          const int64_t i = tid + (int64_t)kBlock * r;
+          const bool in = i < wd.n;
+          const double wi = in ? (a.w ? a.w[wd.n_off + i] : 1.0) : 0.0;
+          kreg[r] = in && wi != 0.0;
+          dreg[r] = kreg[r] ? a.t[wd.n_off + i] - wd.t0 : 0.0;
+        }
+        cached = cur;
+      }
+#pragma unroll
+      for (int r = 0; r < kWinRegs; ++r)
+        if (kreg[r]) fold_point(dreg[r]);
+    } else {
+      for (int64_t i = tid; i < wd.n; i += kBlock) {
+        const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
+        if (wi == 0.0) continue;
+        fold_point(a.t[wd.n_off + i] - wd.t0);
       }
     }
     if (over) atomicOr(a.overflow, 1u);
@@ -968,22 +992,44 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
       const int k = s_k[t];
       const int2 *h = s_mm + t * nb;
       // The window is decided as soon as it holds the required eclipses:
-      // lo/hi only move apart, so stop there.
+      // lo/hi only move apart, so stop there.  Bins are read four at a
+      // time (their loads in flight together) and the test made per group.
       int lo_c = kCycleEmptyLo, hi_c = kCycleEmptyHi;
       const int gap = need2 ? 1 : 0;
       const int first = min(k, nb - j);      // bins j .. nb-1, same cycle
-      for (int m = 0; m < first && hi_c - lo_c < gap; ++m) {
-        const int2 v = h[j + m];
-        lo_c = min(lo_c, v.x);
-        hi_c = max(hi_c, v.y);
+      const int2 empty = make_int2(kCycleEmptyLo, kCycleEmptyHi);
+      for (int m = 0; m < first && hi_c - lo_c < gap; m += 4) {
+        const int2 *q = h + j + m;
+        const int2 v0 = q[0];
+        const int2 v1 = m + 1 < first ? q[1] : empty;
+        const int2 v2 = m + 2 < first ? q[2] : empty;
+        const int2 v3 = m + 3 < first ? q[3] : empty;
+        lo_c = min(min(lo_c, v0.x), min(min(v1.x, v2.x), v3.x));
+        hi_c = max(max(hi_c, v0.y), max(max(v1.y, v2.y), v3.y));
       }
-      for (int m = 0; m < k - first && hi_c - lo_c < gap; ++m) {  // wrapped:
-        const int2 v = h[m];                                       // cycle - 1
-        lo_c = min(lo_c, v.x - 1);
-        hi_c = max(hi_c, v.y - 1);
+      const int wrap = k - first;            // wrapped bins: one cycle earlier
+      for (int m = 0; m < wrap && hi_c - lo_c < gap; m += 4) {
+        const int2 v0 = h[m];
+        const int2 v1 = m + 1 < wrap ? h[m + 1] : empty;
+        const int2 v2 = m + 2 < wrap ? h[m + 2] : empty;
+        const int2 v3 = m + 3 < wrap ? h[m + 3] : empty;
+        lo_c = min(lo_c, min(min(v0.x, v1.x), min(v2.x, v3.x)) - 1);
+        hi_c = max(hi_c, max(max(v0.y, v1.y), max(v2.y, v3.y)) - 1);
       }
       const bool seen = hi_c - lo_c >= gap;
-      if (seen) atomicAdd(&s_count[t], 1);
+      // Count per wave: one LDS add per period present among the active
+      // lanes (a wave's tasks span one or two periods), not one per lane on
+      // the same counter.
+      const unsigned long long hit = __ballot(seen);
+      unsigned long long pending = __ballot(1);
+      while (pending) {
+        const int lead = __ffsll((long long)pending) - 1;
+        const int tl = __shfl(t, lead, 64);
+        const unsigned long long same = __ballot(t == tl) & pending;
+        if ((int)(threadIdx.x & 63) == lead && (hit & same))
+          atomicAdd(&s_count[tl], __popcll(hit & same));
+        pending &= ~same;
+      }
     }
     __syncthreads();
     if (tid < np) out[tid] = s_count[tid];
@@ -1208,10 +1254,10 @@ __host__ __device__ inline int pow2_at_least(int n) {
   return m;
 }
 
-// Forward phase distance from sorted position i to j (one cycle added when
-// the step passes the end of the order).
-__device__ inline double fwd_dist(const double *ph, int i, int j) {
-  return j > i ? ph[j] - ph[i] : (ph[j] + 1.0) - ph[i];
+// Forward phase distance from sorted position i (phase pi) to j (phase pj),
+// one cycle added when the step passes the end of the order.
+__device__ inline double fwd_phase(double pi, double pj, int i, int j) {
+  return j > i ? pj - pi : (pj + 1.0) - pi;
 }
 
 template <bool WEIGHTED, bool DIP>
@@ -1358,43 +1404,74 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     const double Wd = (double)W;
     const double qlo = cd.qlo, qhi = cd.qhi;
 
-    // Runs from every start position.
-    double bv = 0.0;
+    // Runs from every start position.  Four run steps per iteration: their
+    // points and phases are loaded together, then the steps are taken in
+    // order with the same stop rules.  Candidates are compared without a
+    // division (S^2 / den against the lane's best as cross products); the
+    // lane's best value is divided out once at the end.
+    double bnum = 0.0, bden = 1.0;
     unsigned int btie = 0xFFFFFFFFu;
     long long bS = 0, bR = 0;
     for (int r = tid; r < nk; r += kBlock) {
       const int prev = r == 0 ? nk - 1 : r - 1;
-      if (!(fwd_dist(sph, prev, r) > 0.0)) continue;
+      const double ph_r = sph[r], ph_prev = sph[prev];
+      if (!(fwd_phase(ph_prev, ph_r, prev, r) > 0.0)) continue;
       long long S = 0, R = 0;
       int last = r;
-      for (int len = 1; len <= nk - 1; ++len) {
-        S += sq[last];
-        R += WEIGHTED ? (long long)sw[last] : 1ll;
-        const double span = len == 1 ? 0.0 : fwd_dist(sph, r, last);
-        if (!(span < qhi)) break;
-        const int next = last + 1 == nk ? 0 : last + 1;
-        const int cur = last;
-        last = next;
-        if (!(fwd_dist(sph, cur, next) > 0.0)) continue;
-        const double gap = prev == next ? 1.0 : fwd_dist(sph, prev, next);
-        if (!(gap > qlo)) continue;
-        if (len < a.min_in_points) continue;
-        if (DIP && !(S < 0)) continue;
-        const double Rd = (double)R;
-        const double den = Rd * (Wd - Rd);
-        if (!(den > 0.0)) continue;
-        const double Sd = (double)S;
-        const double v = Sd * Sd / den;
-        if (!(v > 0.0)) continue;
-        const unsigned int tie = (unsigned)len * (unsigned)nk + (unsigned)r;
-        if (v > bv || (v == bv && tie < btie)) {
-          bv = v;
-          btie = tie;
-          bS = S;
-          bR = R;
+      bool go = true;
+      for (int len = 1; go && len <= nk - 1; len += 4) {
+        int idx[5];
+        idx[0] = last;
+#pragma unroll
+        for (int u = 1; u < 5; ++u) idx[u] = idx[u - 1] + 1 == nk ? 0 : idx[u - 1] + 1;
+        int qv[4], wv[4];
+        double ph[5];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          qv[u] = sq[idx[u]];
+          wv[u] = WEIGHTED ? sw[idx[u]] : 1;
+          ph[u] = sph[idx[u]];
         }
+        ph[4] = sph[idx[4]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int L = len + u;
+          if (L > nk - 1) {
+            go = false;
+            break;
+          }
+          S += qv[u];
+          R += wv[u];
+          const double span = L == 1 ? 0.0 : fwd_phase(ph_r, ph[u], r, idx[u]);
+          if (!(span < qhi)) {
+            go = false;
+            break;
+          }
+          const int next = idx[u + 1];
+          if (!(fwd_phase(ph[u], ph[u + 1], idx[u], next) > 0.0)) continue;
+          const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, ph[u + 1], prev, next);
+          if (!(gap > qlo)) continue;
+          if (L < a.min_in_points) continue;
+          if (DIP && !(S < 0)) continue;
+          const double Rd = (double)R;
+          const double den = Rd * (Wd - Rd);
+          if (!(den > 0.0) || S == 0) continue;
+          const double Sd = (double)S;
+          const double num = Sd * Sd;
+          const double lhs = num * bden, rhs = bnum * den;
+          const unsigned int tie = (unsigned)L * (unsigned)nk + (unsigned)r;
+          if (lhs > rhs || (lhs == rhs && tie < btie)) {
+            bnum = num;
+            bden = den;
+            btie = tie;
+            bS = S;
+            bR = R;
+          }
+        }
+        last = idx[4];
       }
     }
+    const double bv = bnum > 0.0 ? bnum / bden : 0.0;
     const unsigned long long vb = (unsigned long long)__double_as_longlong(bv);
     if (bv > 0.0) atomicMax(&s_vbits, vb);
     __syncthreads();

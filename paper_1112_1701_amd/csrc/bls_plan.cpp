@@ -931,11 +931,22 @@ int bls_detect_device(bls_plan *p, const bls_batch *b, const float *sr, int32_t 
   a.window = window;
   a.threshold = sde_threshold;
   a.mask_words = (int32_t)std::max<int64_t>(1, (mmax + 31) / 32);
+  if ((e = hipEventRecord(p->ev_search0, s)) != hipSuccess) return hip_error(p, e, "event");
   if ((e = (hipError_t)launch_detect(a, s))) return hip_error(p, e, "launch detection");
+  if ((e = hipEventRecord(p->ev_search1, s)) != hipSuccess) return hip_error(p, e, "event");
   if ((e = hipMemcpyAsync(out, p->d_detect_out, sizeof(bls_detection) * nc,
                           hipMemcpyDeviceToHost, s)) ||
       (e = hipStreamSynchronize(s)))
     return hip_error(p, e, "detection");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1);
+  p->stats = bls_call_stats{};
+  p->stats.search_ms = p->stats.total_ms = ms;
+  double m_total = 0.0;
+  for (int c = 0; c < nc; ++c) m_total += (double)dd[c].nperiods;
+  p->stats.trial_points = m_total;
+  p->stats.block = kBlock;
+  p->stats.grid = nc;
   return BLS_OK;
 }
 
@@ -955,7 +966,9 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
       (!b->p_off && b->nperiods_shared < 1))
     return set_error(p, BLS_ERR_INVALID_ARG, "n_off[0] and p_off[0] must be 0, grid non-empty");
   const int nc = b->ncurves;
-  const int tile = std::max(1, std::min(kTileMax, (32 << 10) / (nphase * 8)));
+  // 16 KB of (min, max) words per workgroup: eight or more workgroups per
+  // CU to overlap the per-item latencies
+  const int tile = std::max(1, std::min(kTileMax, (16 << 10) / (nphase * 8)));
   std::vector<WindowDesc> wd(nc);
   int64_t items = 0, results = 0;
   for (int c = 0; c < nc; ++c) {
