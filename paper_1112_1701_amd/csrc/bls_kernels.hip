@@ -1065,7 +1065,10 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (c >= a.ncurves) return;
+  // The star's offsets and magnitude are loaded together up front (one
+  // round trip before the values, none after them).
   const int64_t off = a.n_off[c], n = a.n_off[c + 1] - off;
+  const double mag = a.mag[c];
   const double *x = a.x + off;
   const double *w = a.w ? a.w + off : nullptr;
   int cnt = 0, bad = 0;
@@ -1127,51 +1130,59 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
   a.rms[c] = sqrt(ss / (double)cnt);
   a.flag[c] = 0;
   int b = -1;
-  const double m = a.mag[c];
-  if (isfinite(m)) {
-    const double q = floor((m - a.origin) / a.width);
+  if (isfinite(mag)) {
+    const double q = floor((mag - a.origin) / a.width);
     if (q >= 0.0 && q < (double)a.nmagbins) b = (int)q;
   }
   a.bin[c] = b;
 }
 
-constexpr int kVarListCap = 1024;   // members kept in LDS per (chip, bin)
+constexpr int kVarRegionCap = 1024;  // members one wave keeps in LDS
 
-// Visit the members of one (chip, bin) in star order: from the LDS list
-// when it holds them all, else by rescanning the chip's stars.
-template <class F>
-__device__ inline void for_members(const int *list, int cnt0, int c0, int c1, int b,
-                                   const int32_t *bin, int lane, F f) {
-  if (cnt0 <= kVarListCap) {
-    for (int i = lane; i < cnt0; i += 64) f(list[i]);
-  } else {
-    for (int st = c0 + lane; st < c1; st += 64)
-      if (bin[st] == b) f(st);
-  }
+// Sum over the workgroup in a fixed order: wave butterflies, then the four
+// wave totals in wave order; every thread receives the same value.
+__device__ inline double block_sum_fixed(double v, double *s_red) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBlock / 64; ++w) t = t + s_red[w];
+  __syncthreads();
+  return t;
 }
 
-// One wave per (chip, bin).
+// One workgroup per (chip, bin).  Each wave scans a quarter of the chip's
+// stars and keeps its members in its own LDS region, so the regions in wave
+// order list the members in star order; a wave with more members than its
+// region holds sends the whole task to rescanning the chip instead.
 __global__ __launch_bounds__(kBlock) void var_clip_kernel(VarArgs a) {
-  __shared__ int s_list[kBlock / 64][kVarListCap];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t task = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  __shared__ int s_list[kBlock / 64][kVarRegionCap];
+  __shared__ double s_val[kBlock / 64][kVarRegionCap];     // members' RMS
+  __shared__ unsigned char s_alive[kBlock / 64][kVarRegionCap];
+  __shared__ int s_wcnt[kBlock / 64];
+  __shared__ double s_red[kBlock / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int64_t task = blockIdx.x;
   if (task >= (int64_t)a.nchips * a.nmagbins) return;
   const int k = (int)(task / a.nmagbins);
   const int b = (int)(task - (int64_t)k * a.nmagbins);
   const int c0 = (int)a.chip_off[k], c1 = (int)a.chip_off[k + 1];
-  int *list = s_list[wv];
+  const int quarter = (c1 - c0 + 3) / 4;
+  const int w0 = min(c1, c0 + wv * quarter), w1 = min(c1, w0 + quarter);
 
-  // Members in star order (ballot compaction), all alive; eight chunks of
-  // bin numbers are loaded together per round.
-  int cnt0 = 0;
+  // Members of this wave's quarter, in star order, all alive; eight chunks
+  // of bin numbers are loaded together per round.
+  int cnt_w = 0;
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int base = c0; base < c1; base += 64 * 8) {
+  for (int base = w0; base < w1; base += 64 * 8) {
     int bv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int st = base + 64 * u + lane;
-      bv[u] = st < c1 ? a.bin[st] : -1;
+      bv[u] = st < w1 ? a.bin[st] : -1;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1179,63 +1190,89 @@ __global__ __launch_bounds__(kBlock) void var_clip_kernel(VarArgs a) {
       const bool mem = bv[u] == b;
       const unsigned long long mask = __ballot(mem);
       if (mem) {
-        const int pos = cnt0 + __popcll(mask & below);
-        if (pos < kVarListCap) list[pos] = st;
+        const int pos = cnt_w + __popcll(mask & below);
+        if (pos < kVarRegionCap) s_list[wv][pos] = st;
         a.alive[st] = 1;
       }
-      cnt0 += __popcll(mask);
+      cnt_w += __popcll(mask);
     }
+  }
+  if (lane == 0) s_wcnt[wv] = cnt_w;
+  __syncthreads();
+  int cnt0 = 0;
+  bool fits = true;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    cnt0 += s_wcnt[w];
+    fits = fits && s_wcnt[w] <= kVarRegionCap;
   }
   const double qnan = __longlong_as_double(0x7ff8000000000000ll);
   if (cnt0 == 0) {
-    if (lane == 0) {
+    if (tid == 0) {
       a.bin_mean[task] = qnan;
       a.bin_std[task] = qnan;
       a.bin_count[task] = 0;
     }
-    return;
+    return;  // uniform: every thread saw cnt0 == 0
   }
+  // Visit the members in star order: the regions in wave order (value and
+  // alive flag in LDS, gathered once), or a rescan of the chip when a region
+  // overflowed.  f(value, alive flag, star).
+  if (fits) {
+    for (int w = 0; w < kBlock / 64; ++w)
+      for (int i = tid; i < s_wcnt[w]; i += kBlock) {
+        s_val[w][i] = a.rms[s_list[w][i]];
+        s_alive[w][i] = 1;
+      }
+    __syncthreads();
+  }
+  auto for_members = [&](auto f) {
+    if (fits) {
+      for (int w = 0; w < kBlock / 64; ++w)
+        for (int i = tid; i < s_wcnt[w]; i += kBlock)
+          f(s_val[w][i], s_alive[w][i], s_list[w][i]);
+    } else {
+      for (int st = c0 + tid; st < c1; st += kBlock)
+        if (a.bin[st] == b) f(a.rms[st], a.alive[st], st);
+    }
+  };
   int cnt = cnt0;
   double mu = 0.0, sd = 0.0;
   for (int it = 0;; ++it) {
-    double s = 0.0;
-    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
-      if (a.alive[st]) s = s + a.rms[st];
+    double sum = 0.0;
+    for_members([&](double v, unsigned char &alive, int) {
+      if (alive) sum = sum + v;
     });
-    mu = wave_sum(s) / (double)cnt;
+    mu = block_sum_fixed(sum, s_red) / (double)cnt;
     double ss = 0.0;
-    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
-      if (a.alive[st]) {
-        const double dv = a.rms[st] - mu;
+    for_members([&](double v, unsigned char &alive, int) {
+      if (alive) {
+        const double dv = v - mu;
         ss = ss + dv * dv;
       }
     });
-    sd = sqrt(wave_sum(ss) / (double)cnt);
+    sd = sqrt(block_sum_fixed(ss, s_red) / (double)cnt);
     if (it >= a.max_iter) break;
     const double lo = mu - a.clip_sigma * sd, hi = mu + a.clip_sigma * sd;
-    int drop = 0;
-    for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
-      if (a.alive[st]) {
-        const double v = a.rms[st];
-        if (!(v >= lo && v <= hi)) {
-          a.alive[st] = 0;
-          ++drop;
-        }
+    double drop = 0.0;
+    for_members([&](double v, unsigned char &alive, int) {
+      if (alive && !(v >= lo && v <= hi)) {
+        alive = 0;
+        drop = drop + 1.0;
       }
     });
-    drop = wave_isum(drop);
-    if (drop == 0) break;
-    cnt -= drop;
+    const int dropped = (int)block_sum_fixed(drop, s_red);
+    if (dropped == 0) break;
+    cnt -= dropped;
   }
-  if (lane == 0) {
+  if (tid == 0) {
     a.bin_mean[task] = mu;
     a.bin_std[task] = sd;
     a.bin_count[task] = cnt;
   }
   if (cnt < a.min_stars) return;
   const double thr = mu + a.flag_sigma * sd;
-  for_members(list, cnt0, c0, c1, b, a.bin, lane, [&](int st) {
-    if (a.rms[st] > thr) a.flag[st] = 1;
+  for_members([&](double v, unsigned char &, int st) {
+    if (v > thr) a.flag[st] = 1;
   });
 }
 
@@ -1620,8 +1657,7 @@ int launch_variability(const VarArgs &a, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   const int64_t tasks = (int64_t)a.nchips * a.nmagbins;
-  hipLaunchKernelGGL(var_clip_kernel, dim3((unsigned)((tasks + per - 1) / per)), dim3(kBlock), 0,
-                     s, a);
+  hipLaunchKernelGGL(var_clip_kernel, dim3((unsigned)tasks), dim3(kBlock), 0, s, a);
   return (int)hipGetLastError();
 }
 

@@ -88,7 +88,8 @@ def _compare(g, o, nk, nb, flag_sigma=2.0):
     (2000, 3, 60, dict(clip_sigma=2.0, max_iter=10)),
     (5000, 11, 60, dict(max_iter=0)),
     (777, 4, 4096, dict(width=0.001)),
-    (3000, 1, 1, dict(width=10.0)),      # one bin beyond the LDS member list
+    (3000, 1, 1, dict(width=10.0)),      # one bin, 750 members per wave
+    (6000, 1, 1, dict(width=10.0)),      # beyond a wave's LDS list: rescan
     (5000, 2, 2, dict(width=3.0, clip_sigma=2.5, max_iter=20)),
     # (clip 1 would shrink sets to two members that sit exactly one
     # deviation from their mean: a tie that rounding decides)
