@@ -48,7 +48,7 @@ bool load_disk(uint64_t key, TileChoice &tc) {
   while (fgets(line, sizeof line, f)) {
     unsigned long long k;
     int budget, cap, occ;
-    if (sscanf(line, "bls-tile-v1 %llx %d %d %d", &k, &budget, &cap, &occ) == 4 && k == key) {
+    if (sscanf(line, "bls-tile-v2 %llx %d %d %d", &k, &budget, &cap, &occ) == 4 && k == key) {
       tc.lds_budget = budget;
       tc.tile_cap = cap;
       tc.occupancy = occ;
@@ -64,7 +64,7 @@ void save_disk(uint64_t key, const TileChoice &tc, double ms) {
   if (!path || !*path) return;
   FILE *f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "bls-tile-v1 %llx %d %d %d %.4f\n", (unsigned long long)key, tc.lds_budget,
+  fprintf(f, "bls-tile-v2 %llx %d %d %d %.4f\n", (unsigned long long)key, tc.lds_budget,
           tc.tile_cap, tc.occupancy, ms);
   fclose(f);
 }
@@ -93,8 +93,7 @@ double time_candidate(bls_plan *p, std::vector<CurveShape> &shapes, bool weighte
                       unsigned long long *keys, int nreps) {
   TileChoice tc;
   const int wpb = weighted ? 2 : 1;
-  const int per_period = (shapes[0].nbins + std::max(shapes[0].kmax - 1, 1)) * 8 * wpb;
-  tc.lds_budget = T * per_period;
+  tc.lds_budget = T * hist_stride(shapes[0].nbins, shapes[0].kmax, T, weighted) * 8 * wpb;
   tc.tile_cap = T;
   PlannedBatch pb;
   if (plan_batch(p, shapes, weighted, tc, pb) != BLS_OK) return -1.0;
@@ -194,11 +193,12 @@ TileChoice tune(bls_plan *p, const Bucket &bk, const CurveShape &rep, bool weigh
       shapes[c].nperiods = m;
     }
     const int wpb = weighted ? 2 : 1;
-    const int per_period = (rep.nbins + std::max(rep.kmax - 1, 1)) * 8 * wpb;
     double best_rate = 0.0;
     const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int T : cands) {
-      if (T > kTileMax || T * per_period > p->max_lds - 1024) break;
+      if (T > kTileMax) break;
+      const int per_period = hist_stride(rep.nbins, rep.kmax, T, weighted) * 8 * wpb;
+      if (T * per_period > p->max_lds - 1024) break;
       const double ms = time_candidate(p, shapes, weighted, T, per, sr, depth, js, ks, keys, 3);
       if (ms <= 0.0) continue;
       const double rate = 1.0 / ms;  // same work for every candidate

@@ -41,7 +41,7 @@ struct CurveDesc {
   int32_t qbits;        // magnitude bits of a point's fixed-point value
   int32_t weighted;     // 1 if a weight array is present
   int32_t check_periods;  // 1: prep checks this curve's trial periods
-  int32_t pad0;
+  int32_t hstride;      // LDS words between periods' histogram planes (>= bins + wrap)
   // ---- written by the prep kernel
   double t0;            // min time over kept points
   double W;             // sum of weights (FP64)

@@ -253,15 +253,17 @@ __device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
 // instruction hold points kPPT apart in time: their phases (hence bins and
 // LDS banks) are far less correlated than those of 64 consecutive points of
 // a sorted light curve, which cuts same-bin and same-bank collisions.
-// Each period's histogram has nb + 1 words: the extra word catches the
-// clamp case and is added to bin nb - 1 when the histogram is decoded.
-// Weighted curves use two such arrays per period, A (count, weight) then B
+// Each period's histogram plane starts HS words after the previous one: nb
+// bins, the word after them (it catches the clamp case and is added to bin
+// nb - 1 when the histogram is decoded, later the start of the wrap-around
+// copy), and padding that keeps the scan's reads free of bank conflicts.
+// Weighted curves use two such planes per period, A (count, weight) then B
 // (weighted signal), each contiguous so that the lanes of one atomic spread
 // over all LDS banks.
 template <bool WEIGHTED, bool FULL>
 __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int64_t base,
                                   int np, const double *s_f, unsigned long long *s_hist,
-                                  int HB) {
+                                  int HS) {
   const int tid = threadIdx.x;
   const int64_t off = cd.n_off;
   const int64_t n = cd.n;
@@ -293,14 +295,14 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   constexpr int wpb = WEIGHTED ? 2 : 1;
   for (int t = 0; t < np; ++t) {
     const double f = s_f[t];
-    unsigned long long *h = s_hist + (size_t)t * HB * wpb;
+    unsigned long long *h = s_hist + (size_t)t * HS * wpb;
 #pragma unroll
     for (int r = 0; r < kPPT; ++r) {
       if (FULL || ok[r]) {
         const int b = raw_bin(d[r], f, nbd);
         __hip_atomic_fetch_add(h + b, va[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (WEIGHTED)
-          __hip_atomic_fetch_add(h + HB + b, vb[r], __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add(h + HS + b, vb[r], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
@@ -567,9 +569,10 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     const int kmin = cd.kmin;
     const int kmax = cd.kmax;
     const int HB = nb + max(kmax - 1, 1);  // bins, then clamp word / wrap copy
+    const int HS = max(cd.hstride, HB);    // words between periods' planes
 
     // Clear the tile's histograms; frequencies f = 1/P (IEEE division).
-    for (int i = tid; i < np * HB * wpb; i += kBlock) s_hist[i] = 0ull;
+    for (int i = tid; i < np * HS * wpb; i += kBlock) s_hist[i] = 0ull;
     if (tid < np) {
       s_f[tid] = 1.0 / a.periods[cd.p_off + p0 + tid];
       s_best[tid] = 0ull;
@@ -580,9 +583,9 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
     // Fold and bin: points in registers, reused for every period of the tile.
     for (int64_t base = 0; base < cd.n; base += (int64_t)kBlock * kPPT) {
       if (base + (int64_t)kBlock * kPPT <= cd.n)
-        fold_chunk<WEIGHTED, true>(a, cd, base, np, s_f, s_hist, HB);
+        fold_chunk<WEIGHTED, true>(a, cd, base, np, s_f, s_hist, HS);
       else
-        fold_chunk<WEIGHTED, false>(a, cd, base, np, s_f, s_hist, HB);
+        fold_chunk<WEIGHTED, false>(a, cd, base, np, s_f, s_hist, HS);
     }
     __syncthreads();
 
@@ -592,19 +595,19 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
       int t = tid / nb, b = tid - (tid / nb) * nb;
       const int dt = kBlock / nb, db = kBlock - (kBlock / nb) * nb;
       for (; t < np;) {
-        unsigned long long *w = s_hist + (size_t)t * HB * wpb + b;
+        unsigned long long *w = s_hist + (size_t)t * HS * wpb + b;
         unsigned long long w0 = w[0];
-        unsigned long long w1 = WEIGHTED ? w[HB] : 0ull;
+        unsigned long long w1 = WEIGHTED ? w[HS] : 0ull;
         if (b == nb - 1) {
           w0 += w[1];
-          if (WEIGHTED) w1 += w[HB + 1];
+          if (WEIGHTED) w1 += w[HS + 1];
         }
         const BinWord bw = decode_word(w0, cd.shift);
         if (WEIGHTED) {
           // A slot <- (R, S) of the bin, B slot <- (count, 0)
           *reinterpret_cast<float2 *>(w) =
               make_float2(int47_to_float(bw.sum) * qscale, int47_to_float((long long)w1) * qscale);
-          *reinterpret_cast<float2 *>(w + HB) = make_float2((float)bw.count, 0.0f);
+          *reinterpret_cast<float2 *>(w + HS) = make_float2((float)bw.count, 0.0f);
           if (bw.count != 0u)
             __hip_atomic_fetch_add(&s_nonempty[t], 1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -627,9 +630,9 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
       for (int i = tid; i < np * ext; i += kBlock) {
         const int t = i / ext;
         const int e = i - t * ext;
-        unsigned long long *src = s_hist + (size_t)t * HB * wpb + e;
+        unsigned long long *src = s_hist + (size_t)t * HS * wpb + e;
         src[nb] = src[0];
-        if (WEIGHTED) src[HB + nb] = src[HB];
+        if (WEIGHTED) src[HS + nb] = src[HS];
       }
     }
     __syncthreads();
@@ -653,12 +656,12 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         float bn, bd;
         int bm;
         if (WEIGHTED) {
-          const float2 *ha = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HB * 2) + j;
+          const float2 *ha = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HS * 2) + j;
           const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
-          scan_task_weighted<DIP>(ha, ha + HB, kmin, kmax, Wf, thr, nmax1, mipf, need_counts, bn,
+          scan_task_weighted<DIP>(ha, ha + HS, kmin, kmax, Wf, thr, nmax1, mipf, need_counts, bn,
                                   bd, bm);
         } else {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
+          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HS + j;
           if (mip1)
             scan_task_unit<DIP, true>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
           else
@@ -702,13 +705,13 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         // S in the scan's order; R (exact counts for unit weights)
         float R = 0.0f, S = 0.0f;
         if (WEIGHTED) {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HB * 2) + j;
+          const float2 *h = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HS * 2) + j;
           for (int m = 0; m < k; ++m) {
             R += h[m].x;
             S += h[m].y;
           }
         } else {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HB + j;
+          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HS + j;
           for (int m = 0; m < k; ++m) {
             R += h[m].x;
             S += h[m].y;

@@ -14,8 +14,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <numeric>
+#include <unordered_map>
 
 namespace bls {
 namespace {
@@ -82,6 +84,85 @@ int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t 
   if (kmin) *kmin = (int32_t)lo;
   if (kmax) *kmax = (int32_t)hi;
   return lo <= hi ? BLS_OK : BLS_ERR_INVALID_ARG;
+}
+
+namespace {
+
+// Cycles the scan's 64-bit LDS reads take for the first rounds of lane tasks
+// of one workgroup when consecutive periods' planes are S float2 apart.  The
+// LDS serves such reads 16 lanes at a time from 32 banks of 4 bytes: a group
+// of 16 lanes takes as many cycles as the busiest bank has accesses.  Lane
+// task q is (start bin, period) = divmod(q, tile); every lane reads at the
+// same offset m past its own start, which moves all banks alike, so m = 0.
+int scan_read_cycles(int S, int tile, int nbins) {
+  int cycles = 0;
+  for (int round = 0; round < 4; ++round) {
+    for (int g = 0; g < kBlock / 16; ++g) {
+      int bank[32] = {0};
+      int worst = 0;
+      for (int l = 0; l < 16; ++l) {
+        const int q = round * kBlock + g * 16 + l;
+        const int j = q / tile, t = q - (q / tile) * tile;
+        if (j >= nbins) continue;
+        const int b0 = (int)((2 * ((int64_t)t * S + j)) & 31);
+        worst = std::max(worst, ++bank[b0]);
+        worst = std::max(worst, ++bank[(b0 + 1) & 31]);
+      }
+      cycles += worst;
+    }
+  }
+  return cycles;
+}
+
+// Banks depend on S mod 16 only; the cost of each residue is kept.
+int cached_read_cycles(int S, int tile, int nbins) {
+  static std::mutex mu;
+  static std::unordered_map<uint64_t, int> memo;
+  const int nb = std::min(nbins, 4 * kBlock);  // lanes reach no further start bin
+  const uint64_t key = ((uint64_t)nb << 16) | ((uint64_t)tile << 4) | (uint64_t)(S & 15);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  const int c = scan_read_cycles(S & 15, tile, nb);
+  std::lock_guard<std::mutex> g(mu);
+  memo.emplace(key, c);
+  return c;
+}
+
+}  // namespace
+
+int hist_words(int nbins, int kmax) { return nbins + std::max(kmax - 1, 1); }
+
+int hist_stride(int nbins, int kmax, int tile, bool weighted) {
+  const int hb = hist_words(nbins, kmax);
+  const int wpb = weighted ? 2 : 1;  // the scan reads the first plane of wpb
+  int best = hb, best_cost = 0;
+  for (int hs = hb; hs < hb + 16; ++hs) {
+    const int c = cached_read_cycles(hs * wpb, tile, nbins);
+    if (hs == hb || c < best_cost) {
+      best = hs;
+      best_cost = c;
+    }
+  }
+  return best;
+}
+
+void fit_tile(int nbins, int kmax, int64_t nperiods, int lds_budget, int tile_cap,
+              bool weighted, int *tile, int *stride) {
+  const int wpb = weighted ? 2 : 1;
+  int T = std::max(1, lds_budget / (hist_words(nbins, kmax) * 8 * wpb));
+  T = std::min(T, std::min(tile_cap, kTileMax));
+  T = (int)std::min<int64_t>(T, std::max<int64_t>(nperiods, 1));
+  T = std::max(T, 1);
+  int hs = hist_stride(nbins, kmax, T, weighted);
+  while (T > 1 && T * hs * 8 * wpb > lds_budget) {
+    --T;
+    hs = hist_stride(nbins, kmax, T, weighted);
+  }
+  *tile = T;
+  *stride = hs;
 }
 
 int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
@@ -304,14 +385,13 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
     d.weighted = weighted ? 1 : 0;
     // each distinct period range is checked once (a shared grid by curve 0)
     d.check_periods = (c == 0 || s.p_off != shapes[0].p_off) ? 1 : 0;
-    // bins, then the clamp word / wrap-around copy (at least one word), as
-    // the kernel lays them out
-    const int per_period = (s.nbins + std::max(s.kmax - 1, 1)) * 8 * wpb;
-    int T = std::max(1, tc.lds_budget / per_period);
-    T = std::min(T, std::min(tc.tile_cap, kTileMax));
-    T = std::min(T, s.nperiods);
+    // bins, then the clamp word / wrap-around copy, per period and plane,
+    // padded against LDS bank conflicts, as the kernel lays them out
+    int T = 1, hs = 0;
+    fit_tile(s.nbins, s.kmax, s.nperiods, tc.lds_budget, tc.tile_cap, weighted, &T, &hs);
     d.tile = T;
-    hist_bytes = std::max(hist_bytes, T * per_period);
+    d.hstride = hs;
+    hist_bytes = std::max(hist_bytes, T * hs * 8 * wpb);
     const double nw = (double)(s.kmax - s.kmin + 1);
     item_cost[c] = (double)T * ((double)s.n + 1.6 * (double)s.nbins * nw);
     out.total_points += s.n;

@@ -142,6 +142,19 @@ int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t 
 // Device allocation with the optional failure-injection hook.
 hipError_t device_alloc(void **ptr, size_t bytes);
 
+// LDS words (64-bit) one period's histogram plane needs: the bins, then the
+// clamp word / wrap-around copy of the first kmax - 1 bins.
+int hist_words(int nbins, int kmax);
+// Words between consecutive periods' planes for a tile of `tile` periods:
+// at least hist_words, padded so that the scan's 64-bit reads, served 16
+// lanes at a time across 32 four-byte banks, meet as few bank conflicts as
+// the layout allows (lane task (start bin, period) = divmod(lane, tile)).
+int hist_stride(int nbins, int kmax, int tile, bool weighted);
+// Periods per work item that fit an LDS budget (at least one, at most
+// tile_cap and nperiods) and the padded stride that goes with it.
+void fit_tile(int nbins, int kmax, int64_t nperiods, int lds_budget, int tile_cap,
+              bool weighted, int *tile, int *stride);
+
 // Tile choice for a batch: autotuned (cached) unless disabled.
 TileChoice choose_tiles(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted);
 // The built-in table the tuner starts from.

@@ -44,7 +44,7 @@ struct Req {
   int64_t best = -1;
   int slot = -1;
   size_t pt_off = 0, pr_off = 0;
-  int32_t tile = 1, ntiles = 0, issued = 0, done_tiles = 0;
+  int32_t tile = 1, hstride = 0, ntiles = 0, issued = 0, done_tiles = 0;
   double item_cost = 0;
   uint64_t order = 0;
   double pp = 0, evals = 0;
@@ -159,6 +159,7 @@ hipError_t start_request(bls_server *s, Req *r) {
   d.kmin = r->kmin;
   d.kmax = r->kmax;
   d.tile = r->tile;
+  d.hstride = r->hstride;
   const int cb = cbits_of(r->n);
   d.shift = 64 - cb;
   d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
@@ -201,7 +202,7 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
     s->h_seg_tile0[b][i] = g.tile0;
     items += g.ntiles;
     const Req *r = s->slots[g.slot];
-    hist_bytes = std::max(hist_bytes, r->tile * (r->nbins + std::max(r->kmax - 1, 1)) * 8 * wpb);
+    hist_bytes = std::max(hist_bytes, r->tile * r->hstride * 8 * wpb);
   }
   const int nseg = (int)tk.segs.size();
   s->h_seg_start[b][nseg] = items;
@@ -619,10 +620,11 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
     }
   }
   const int wpb = r->weighted ? 2 : 1;
-  const int per_period = (r->nbins + std::max(r->kmax - 1, 1)) * 8 * wpb;
-  int T = std::max(1, s->lds_budget / per_period);
-  T = std::min<int64_t>(std::min(T, kTileMax), r->np);
+  int T = 1, hs = 0;
+  fit_tile(r->nbins, r->kmax, r->np, s->lds_budget, kTileMax, r->weighted, &T, &hs);
+  const int per_period = hs * 8 * wpb;
   r->tile = T;
+  r->hstride = hs;
   r->ntiles = (int32_t)((r->np + T - 1) / T);
   const double nw = (double)(r->kmax - r->kmin + 1);
   r->item_cost = (double)T * ((double)r->n + 1.6 * (double)r->nbins * nw);
