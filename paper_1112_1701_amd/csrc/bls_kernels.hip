@@ -357,15 +357,25 @@ __device__ __forceinline__ void scan_task_unit(const float2 *h, int kmin, int km
     const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
     const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
     const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
-    const bool p0 = S0 * S0 >= u0 * d0;
-    const bool p1 = S1 * S1 >= u1 * d1;
-    const bool p2 = S2 * S2 >= u2 * d2;
-    const bool p3 = S3 * S3 >= u3 * d3;
-    if (p0 | p1 | p2 | p3) {
-      if (p0) consider<false, DIP, MIP1>(Wf - d0, S0, 0.f, d0, m, 0.f, mipf, bn, bd, bm);
-      if (p1) consider<false, DIP, MIP1>(Wf - d1, S1, 0.f, d1, m + 1, 0.f, mipf, bn, bd, bm);
-      if (p2) consider<false, DIP, MIP1>(Wf - d2, S2, 0.f, d2, m + 2, 0.f, mipf, bn, bd, bm);
-      if (p3) consider<false, DIP, MIP1>(Wf - d3, S3, 0.f, d3, m + 3, 0.f, mipf, bn, bd, bm);
+    // x = S^2 - u d; one comparison of the largest of the four decides
+    // whether any of them needs the exact test.
+    const float x0 = fmaf(-u0, d0, S0 * S0);
+    const float x1 = fmaf(-u1, d1, S1 * S1);
+    const float x2 = fmaf(-u2, d2, S2 * S2);
+    const float x3 = fmaf(-u3, d3, S3 * S3);
+    if (fmaxf(fmaxf(x0, x1), fmaxf(x2, x3)) >= 0.0f) {
+      // Rare: the four boxes again from the group's start, in the same
+      // operations (so the same values), each to the exact test if it passed.
+      float dd = d, SS = S, uu = u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 e = h[m + i];
+        dd -= e.x;
+        SS += e.y;
+        uu = fmaf(thr, e.x, uu);
+        if (fmaf(-uu, dd, SS * SS) >= 0.0f)
+          consider<false, DIP, MIP1>(Wf - dd, SS, 0.f, dd, m + i, 0.f, mipf, bn, bd, bm);
+      }
     }
     d = d3;
     S = S3;
@@ -431,15 +441,23 @@ __device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float
     const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
     const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
     const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
-    const bool p0 = S0 * S0 >= u0 * d0;
-    const bool p1 = S1 * S1 >= u1 * d1;
-    const bool p2 = S2 * S2 >= u2 * d2;
-    const bool p3 = S3 * S3 >= u3 * d3;
-    if (p0 | p1 | p2 | p3) {
-      if (p0) consider_w<DIP>(Wf - d0, S0, d0, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
-      if (p1) consider_w<DIP>(Wf - d1, S1, d1, m + 1, hc, need_counts, nmax1, mipf, bn, bd, bm);
-      if (p2) consider_w<DIP>(Wf - d2, S2, d2, m + 2, hc, need_counts, nmax1, mipf, bn, bd, bm);
-      if (p3) consider_w<DIP>(Wf - d3, S3, d3, m + 3, hc, need_counts, nmax1, mipf, bn, bd, bm);
+    // as for unit weights: the largest x = S^2 - u d of the four decides,
+    // and the rare boxes that pass are recomputed from the group's start
+    const float x0 = fmaf(-u0, d0, S0 * S0);
+    const float x1 = fmaf(-u1, d1, S1 * S1);
+    const float x2 = fmaf(-u2, d2, S2 * S2);
+    const float x3 = fmaf(-u3, d3, S3 * S3);
+    if (fmaxf(fmaxf(x0, x1), fmaxf(x2, x3)) >= 0.0f) {
+      float dd = d, SS = S, uu = u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 e = ha[m + i];
+        dd -= e.x;
+        SS += e.y;
+        uu = fmaf(thr, e.x, uu);
+        if (fmaf(-uu, dd, SS * SS) >= 0.0f)
+          consider_w<DIP>(Wf - dd, SS, dd, m + i, hc, need_counts, nmax1, mipf, bn, bd, bm);
+      }
     }
     d = d3;
     S = S3;
@@ -453,6 +471,14 @@ __device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float
     if (S * S >= u * d)
       consider_w<DIP>(Wf - d, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
   }
+}
+
+// Key of a lane's best box: its value (any consistent rounding; exact ties
+// compare equal), then the smaller width and start.
+__device__ __forceinline__ unsigned long long box_key(float bn, float bd, int bm, int j, int nb) {
+  const float v = bn * __builtin_amdgcn_rcpf(bd);
+  const unsigned idx = __umul24((unsigned)(bm + 1), (unsigned)nb) + (unsigned)j;
+  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
 // Next work item of a persistent workgroup (thread 0 only): items of its
@@ -516,7 +542,8 @@ __device__ inline ItemRef claim_item(const SearchArgs &a, unsigned &done_mask, S
 }
 
 template <bool WEIGHTED, bool DIP>
-__global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEIGHTED ? 1 : 7)))
+void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
   __shared__ double s_f[kTileMax];
   __shared__ unsigned long long s_best[kTileMax];
@@ -656,26 +683,22 @@ __global__ __launch_bounds__(kBlock) void search_kernel(SearchArgs a) {
         float bn, bd;
         int bm;
         if (WEIGHTED) {
-          const float2 *ha = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HS * 2) + j;
+          const float2 *ha = reinterpret_cast<const float2 *>(s_hist) +
+                             __umul24((unsigned)t, (unsigned)(2 * HS)) + j;
           const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
           scan_task_weighted<DIP>(ha, ha + HS, kmin, kmax, Wf, thr, nmax1, mipf, need_counts, bn,
                                   bd, bm);
         } else {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HS + j;
+          const float2 *h =
+              reinterpret_cast<const float2 *>(s_hist) + __umul24((unsigned)t, (unsigned)HS) + j;
           if (mip1)
             scan_task_unit<DIP, true>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
           else
             scan_task_unit<DIP, false>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
         }
-        if (bm >= 0) {
-          // Key: value (any consistent rounding; exact ties compare equal),
-          // then the smaller width and start.
-          const float v = bn * __builtin_amdgcn_rcpf(bd);
-          const unsigned idx = (unsigned)((bm + 1) * nb + j);
-          const unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                                         (unsigned long long)(0xFFFFFFFFu - idx);
-          __hip_atomic_fetch_max(&s_best[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        if (bm >= 0)
+          __hip_atomic_fetch_max(&s_best[t], box_key(bn, bd, bm, j, nb), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         t += dtt;
         j += dj;
         if (t >= np) {
