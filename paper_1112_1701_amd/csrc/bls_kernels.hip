@@ -481,6 +481,41 @@ __device__ __forceinline__ unsigned long long box_key(float bn, float bd, int bm
   return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
+// Seed of a weighted curve's per-period best before the scan: kSeeds boxes
+// of width kmin with start bins spread over the period (a box may run into
+// the wrap-around copy), each evaluated as a lane task evaluates it: the same
+// sums in the same order, the same validity test and the same key.  Without
+// it the first round of lane tasks screens against zero and sends every box
+// to the exact test, whose count sums make that costly for weighted curves.
+// Seed keys are keys of valid boxes, so the period's largest key stands.
+constexpr int kSeeds = 32;
+
+template <bool DIP>
+__device__ inline void seed_best_weighted(const unsigned long long *s_hist,
+                                          unsigned long long *s_best, const int *s_nonempty,
+                                          int np, int nb, int HS, int kmin, int kmax, float Wf,
+                                          float nmax1, float mipf, bool mip1) {
+  for (int q = threadIdx.x; q < np * kSeeds; q += kBlock) {
+    const int t = q / kSeeds;
+    const int j = (int)(__umul24((unsigned)(q % kSeeds), (unsigned)nb) / kSeeds);
+    const float2 *h =
+        reinterpret_cast<const float2 *>(s_hist) + __umul24((unsigned)t, (unsigned)(2 * HS)) + j;
+    float d = Wf, S = 0.0f;
+    for (int i = 0; i < kmin; ++i) {
+      const float2 e = h[i];
+      d -= e.x;
+      S += e.y;
+    }
+    float bn = 0.0f, bd = 1.0f;
+    int bm = -1;
+    const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
+    consider_w<DIP>(Wf - d, S, d, kmin - 1, h + HS, need_counts, nmax1, mipf, bn, bd, bm);
+    if (bm >= 0)
+      __hip_atomic_fetch_max(&s_best[t], box_key(bn, bd, bm, j, nb), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 // Next work item of a persistent workgroup (thread 0 only): items of its
 // own partition first, then of the others in turn; -1 once all are taken.
 // done_mask remembers the partitions found empty.
@@ -663,6 +698,12 @@ void search_kernel(SearchArgs a) {
       }
     }
     __syncthreads();
+    if (WEIGHTED) {
+      seed_best_weighted<DIP>(s_hist, s_best, s_nonempty, np, nb, HS, kmin, kmax, cd.Wf,
+                              (float)(cd.n_eff - 1), (float)a.min_in_points,
+                              a.min_in_points <= 1);
+      __syncthreads();
+    }
 
     // Box scan.  Lane task = (start bin j, period t), start-bin major, so that
     // the per-period best found by earlier tasks (s_best) is already a good

@@ -68,6 +68,23 @@ def test_small_curves(bls, plan, n, nper, nbins, weighted):
     check_curve(lc, _run(bls, plan, lc), _orc(lc), label="small%d" % n)
 
 
+@pytest.mark.parametrize("n,nbins,dip", [(30, 400, False), (60, 200, False),
+                                         (45, 300, True)])
+def test_sparse_bins_empty_boxes(bls, plan, n, nbins, dip):
+    """Far fewer points than bins: most narrow boxes hold no point, so their
+    statistic is 0/0 and they must never be taken, neither on their own nor
+    on a tie with another box of equal (zero) products."""
+    lc = synth.small_curve(7000 + n, n, nperiods=40, nbins=nbins, qmin=0.005,
+                           qmax=0.05)
+    _say("sparse bins", n, nbins, dip)
+    flags = bls.BLS_DIP_ONLY if dip else 0
+    with bls.Plan(max_curves=4, max_points=1 << 12, max_periods=1 << 10,
+                  max_nbins=nbins, flags=flags) as p:
+        g = _run(bls, p.handle, lc)
+    assert np.all(np.isfinite(g["sr"])), "non-finite SR"
+    check_curve(lc, g, _orc(lc, dip_only=dip), label="sparse%d" % n)
+
+
 def test_single_period_and_widest_boxes(bls, plan):
     lc = synth.small_curve(5, 400, nperiods=1, nbins=50, qmin=0.01,
                            qmax=0.999)
