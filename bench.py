@@ -14,6 +14,10 @@ batched throughput, the plain per-curve GPU form for comparison, and the
 oracle; then the serving workload swept over Poisson arrival rates with
 p50/p99 latency; then the eclipse-window, variability and unbinned
 workloads, each with its kernel time, roofline and oracle.
+
+--copy-calibration: three plain device copies of 1 GiB and nothing else,
+the reference run that scales the HBM traffic counters (FETCH_SIZE,
+WRITE_SIZE) to bytes.
 """
 from __future__ import annotations
 
@@ -28,15 +32,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue rate of gfx950: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
-# 32- or 64-bit add/mul/compare per lane per clock (= 78.6 TFLOP/s FP64 or
-# non-packed FP32 when an FMA counts as two).
-PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic operations: per trial-period x point the fold (multiply,
-# floor, subtract, multiply, truncate) and one accumulation; per box
-# evaluation two running sums, W - R, R (W - R), S^2 and one comparison.
-OPS_PER_TRIAL_POINT = 6
-OPS_PER_BOX_EVAL = 6
+# VALU issue of gfx950, counted in FP32 issue slots: FP32 vector
+# instructions issue at 128 lanes per CU per clock (256 CUs x 128 x 2.4 GHz
+# = 78.6 T lane-ops/s, the published 157.3 TFLOP/s FP32 vector peak with an
+# FMA as two), FP64 and 32-bit integer ones at half that (78.6 TFLOP/s FP64),
+# so each of those takes two slots.  The ALU rooflines quote two FLOP per
+# slot, which makes their peak the published 157.3 TFLOP/s.
+FP32_SLOTS_PER_S = 256 * 128 * 2.4e9
+ALU_PEAK_TFLOPS = 2 * FP32_SLOTS_PER_S / 1e12
+# Algorithmic slots: per trial-period x point the fold, four FP64 operations
+# (multiply, fractional part, multiply, truncate) and one integer (the bin
+# address), 2 slots each; per box evaluation six FP32 operations (the two
+# running sums, theta R, S^2, S^2 - theta R (W - R) and the comparison).
+SLOTS_PER_TRIAL_POINT = 10
+SLOTS_PER_BOX_EVAL = 6
 
 
 def log(*a):
@@ -193,11 +202,10 @@ def measured_traffic():
 
 
 def roofline(pp, evals, k_ms, traffic=None):
-    ops = OPS_PER_TRIAL_POINT * pp + OPS_PER_BOX_EVAL * evals
-    achieved = ops / (k_ms * 1e-3) / 1e12
-    peak = PEAK_VALU_OPS / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic}
+    r = _alu_roofline(SLOTS_PER_TRIAL_POINT * pp + SLOTS_PER_BOX_EVAL * evals,
+                      k_ms)
+    r["traffic"] = traffic
+    return r
 
 
 def headline(args):
@@ -333,16 +341,22 @@ def suite_serving(bls, rates, pool_size, max_requests, seconds):
 # (period, trial epoch) one window decision (min, max, compare, count);
 # unbinned search: per point x period the fold and rank (10), per run step
 # the two exact sums, span and gap distances, S^2, R (W - R), compare (8).
-OPS_WINDOW_PP, OPS_WINDOW_EPOCH = 7, 4
-OPS_UNBINNED_PP, OPS_UNBINNED_STEP = 10, 8
+# FP32 issue slots of the other searches (their work is FP64 and integer,
+# two slots per operation): the eclipse window's fold (multiply, fractional
+# part, multiply, truncate, address) per point x period and four integer
+# operations per epoch decision; the unbinned search's phase and counting
+# sort (10 operations) per point x period and its 8 integer operations per
+# run step.
+SLOTS_WINDOW_PP, SLOTS_WINDOW_EPOCH = 10, 8
+SLOTS_UNBINNED_PP, SLOTS_UNBINNED_STEP = 20, 16
 HBM_PEAK_GBS = 8000.0
 
 
-def _alu_roofline(ops, k_ms):
-    achieved = ops / (k_ms * 1e-3) / 1e12
-    peak = PEAK_VALU_OPS / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+def _alu_roofline(slots, k_ms):
+    achieved = 2 * slots / (k_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
+            "traffic": None}
 
 
 def _median(v):
@@ -399,8 +413,8 @@ def suite_window(args, bls):
             "trial_points_per_s": pp / (k_ms * 1e-3),
             "launch": {"grid": st["grid"], "lds_bytes": st["lds_bytes"],
                        "work_items": st["work_items"]},
-            "roofline": _alu_roofline(OPS_WINDOW_PP * pp +
-                                      OPS_WINDOW_EPOCH * dec, k_ms),
+            "roofline": _alu_roofline(SLOTS_WINDOW_PP * pp +
+                                      SLOTS_WINDOW_EPOCH * dec, k_ms),
             "cpu_baseline": cpu}
 
 
@@ -503,8 +517,8 @@ def suite_unbinned(args, bls):
             "trial_points_per_s": pp / (k_ms * 1e-3),
             "launch": {"grid": st["grid"], "lds_bytes": st["lds_bytes"],
                        "work_items": st["work_items"]},
-            "roofline": _alu_roofline(OPS_UNBINNED_PP * pp +
-                                      OPS_UNBINNED_STEP * steps, k_ms),
+            "roofline": _alu_roofline(SLOTS_UNBINNED_PP * pp +
+                                      SLOTS_UNBINNED_STEP * steps, k_ms),
             "cpu_baseline": cpu}
 
 
@@ -596,6 +610,18 @@ def _as_batch(lc):
                        [lc.truth])
 
 
+def copy_calibration():
+    """Three device copies of 2^28 float32 (1 GiB each), for the counters."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copied 3 x 1 GiB")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -612,13 +638,16 @@ def main():
     ap.add_argument("--pool", type=int, default=300)
     ap.add_argument("--max-requests", type=int, default=1500)
     ap.add_argument("--seconds", type=float, default=3.0)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the search shards by curve with "
               "no collective, and this build measures the single-GPU kernel "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.suite:
+    if args.copy_calibration:
+        copy_calibration()
+    elif args.suite:
         suite(args)
     else:
         headline(args)
