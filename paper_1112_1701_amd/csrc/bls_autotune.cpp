@@ -194,7 +194,10 @@ TileChoice tune(bls_plan *p, const Bucket &bk, const CurveShape &rep, bool weigh
     }
     const int wpb = weighted ? 2 : 1;
     double best_rate = 0.0;
-    const int cands[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    // Tiles of 4, 5, 7, 8, 9 and 16 periods can read bins free of LDS bank
+    // conflicts, 6, 10 and 12 cannot; 7 is the largest that lets eight
+    // unit-weight workgroups share a CU at 300 bins.
+    const int cands[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16, 24, 32};
     for (int T : cands) {
       if (T > kTileMax) break;
       const int per_period = hist_stride(rep.nbins, rep.kmax, T, weighted) * 8 * wpb;
