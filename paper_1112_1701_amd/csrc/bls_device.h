@@ -52,7 +52,7 @@ struct CurveDesc {
   int32_t status;       // CurveStatus
   int32_t es;           // exponent of the S fixed-point scale
   int32_t ew;           // exponent of the weight fixed-point scale
-  int32_t pad;
+  float cadence;        // median gap between consecutive input times (sampled)
   // ---- unbinned search only (host)
   double qlo;           // duty-cycle limits of a box, in phase
   double qhi;

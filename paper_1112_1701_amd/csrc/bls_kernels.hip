@@ -155,6 +155,21 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
   const double W = weighted ? sw : (double)cnt;
   const double xbar = swx / sw;
 
+  // Cadence: the lower median of 64 gaps between consecutive input times,
+  // sampled evenly along the curve (the fold spaces its lanes by it; any
+  // value is correct, a good one only makes the fold faster).
+  if (tid < 64) {
+    const int64_t i = (int64_t)tid * (n - 1) / 64;
+    float g = fabsf((float)(a.t[off + i + 1] - a.t[off + i]));
+    if (!isfinite(g)) g = INFINITY;
+    int rank = 0;
+    for (int k = 0; k < 64; ++k) {
+      const float o = __shfl(g, k, 64);
+      rank += (o < g) || (o == g && k < tid);
+    }
+    if (rank == 31) cd->cadence = g;
+  }
+
   // Pass 2: largest |w (x - xbar)| and largest w, for the fixed-point scales.
   double my = 0.0, mw = 0.0;
   for (int64_t i = tid; i < n; i += kBlock) {
@@ -248,6 +263,29 @@ __device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
   return (int)min((unsigned)raw_bin(d, f, nbd), nbm1);
 }
 
+// A 64-bit value every lane holds alike, moved to scalar registers.
+__device__ inline int64_t uniform_i64(int64_t v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)v & 0xFFFFFFFFu));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Lane spacing of the fold for one work item, in units of kPPT points:
+// 1, 2 or 4 (a chunk is kBlock / 64 = 4 waves of 64 lanes).  On a dense
+// cadence, points close in time fall into one bin at long periods, and
+// lanes of one LDS atomic on the same word are serialised.  The gap is
+// the smallest that puts adjacent lanes half a bin apart in phase at the
+// tile's longest period (fmin = its smallest frequency); cadence is the
+// curve's median time step.  Where lanes are that far apart already, the
+// contiguous layout (gap 1) is the faster one.
+static_assert(kBlock == 256 && kPPT == 4, "the fold's lane layout assumes 4 waves of 4 points");
+
+__device__ inline int fold_lane_gap(double fmin, int nbins, float cadence) {
+  // x = (lane step in time) / (bin width in time at the longest period)
+  const double x = fmin * (double)nbins * (double)kPPT * (double)cadence;
+  return !(x < 0.5) || !(x > 0.0) ? 1 : x >= 0.25 ? 2 : 4;
+}
+
 // Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
 // Each thread takes kPPT consecutive points, so the 64 lanes of one atomic
 // instruction hold points kPPT apart in time: their phases (hence bins and
@@ -263,10 +301,22 @@ __device__ inline int phase_bin(double d, double f, double nbd, unsigned nbm1) {
 template <bool WEIGHTED, bool FULL>
 __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int64_t base,
                                   int np, const double *s_f, unsigned long long *s_hist,
-                                  int HS) {
+                                  int HS, int gap) {
   const int tid = threadIdx.x;
-  const int64_t off = cd.n_off;
-  const int64_t n = cd.n;
+  // The chunk's first point and the points left from there, kept in scalar
+  // registers.
+  const int64_t off = uniform_i64(cd.n_off + base);
+  const int64_t left = uniform_i64(cd.n - base);
+  // Each thread takes kPPT consecutive points; the lanes of a wave are
+  // kPPT gap points apart and the waves interleave (gap 1, 2 or 4).  The
+  // gap passes through an opaque copy so that the compiler recomputes this
+  // per chunk instead of holding it in VGPRs through the item.
+  asm volatile("" : "+s"(gap));
+  const int w = tid >> 6, l = tid & 63;
+  const int k0 = kPPT * (l * gap + (w & (gap - 1))) + 64 * kPPT * gap * (w >> (gap >> 1));
+  const double *dt = a.dt + off;
+  const int32_t *q = a.q + off;
+  const int32_t *qw = WEIGHTED ? a.qw + off : nullptr;
   const double nbd = (double)cd.nbins;
   const unsigned long long one = 1ull << cd.shift;
   double d[kPPT];
@@ -275,16 +325,16 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   bool ok[kPPT];
 #pragma unroll
   for (int r = 0; r < kPPT; ++r) {
-    const int64_t i = base + (int64_t)tid * kPPT + r;
-    ok[r] = FULL || i < n;
+    const int k = k0 + r;
+    ok[r] = FULL || (int64_t)k < left;
     d[r] = 0.0;
     va[r] = 0;
     vb[r] = 0;
     if (ok[r]) {
-      d[r] = a.dt[off + i];
-      const long long qi = a.q[off + i];
+      d[r] = dt[k];
+      const long long qi = q[k];
       if (WEIGHTED) {
-        const int qwi = a.qw[off + i];
+        const int qwi = qw[k];
         va[r] = qwi >= 0 ? one + (unsigned long long)(long long)qwi : 0ull;
         vb[r] = (unsigned long long)qi;
       } else {
@@ -643,13 +693,17 @@ void search_kernel(SearchArgs a) {
       s_nonempty[tid] = 0;
     }
     __syncthreads();
+    // the tile's longest period, taken from its ends (period grids are
+    // ordered in practice; another choice only changes the speed)
+    const int lanes_gap = __builtin_amdgcn_readfirstlane(
+        fold_lane_gap(fmin(s_f[0], s_f[np - 1]), cd.nbins, cd.cadence));
 
     // Fold and bin: points in registers, reused for every period of the tile.
     for (int64_t base = 0; base < cd.n; base += (int64_t)kBlock * kPPT) {
       if (base + (int64_t)kBlock * kPPT <= cd.n)
-        fold_chunk<WEIGHTED, true>(a, cd, base, np, s_f, s_hist, HS);
+        fold_chunk<WEIGHTED, true>(a, cd, base, np, s_f, s_hist, HS, lanes_gap);
       else
-        fold_chunk<WEIGHTED, false>(a, cd, base, np, s_f, s_hist, HS);
+        fold_chunk<WEIGHTED, false>(a, cd, base, np, s_f, s_hist, HS, 1);
     }
     __syncthreads();
 
