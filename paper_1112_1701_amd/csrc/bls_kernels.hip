@@ -346,14 +346,27 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
   for (int t = 0; t < np; ++t) {
     const double f = s_f[t];
     unsigned long long *h = s_hist + (size_t)t * HS * wpb;
+    // A thread's consecutive points that share a bin (common at long
+    // periods) are summed in registers and sent as one atomic.
+    int bin[kPPT];
+#pragma unroll
+    for (int r = 0; r < kPPT; ++r) bin[r] = raw_bin(d[r], f, nbd);
+    unsigned long long accA = 0, accB = 0;
 #pragma unroll
     for (int r = 0; r < kPPT; ++r) {
       if (FULL || ok[r]) {
-        const int b = raw_bin(d[r], f, nbd);
-        __hip_atomic_fetch_add(h + b, va[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (WEIGHTED)
-          __hip_atomic_fetch_add(h + HS + b, vb[r], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        accA += va[r];
+        if (WEIGHTED) accB += vb[r];
+        const int rn = r + 1 < kPPT ? r + 1 : r;
+        const bool run_ends = r == kPPT - 1 || !(FULL || ok[rn]) || bin[rn] != bin[r];
+        if (run_ends) {
+          __hip_atomic_fetch_add(h + bin[r], accA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (WEIGHTED)
+            __hip_atomic_fetch_add(h + HS + bin[r], accB, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          accA = 0;
+          accB = 0;
+        }
       }
     }
   }
