@@ -642,7 +642,7 @@ __device__ inline ItemRef claim_item(const SearchArgs &a, unsigned &done_mask, S
 // Unit-weight kernels are held to 64 VGPRs (8 waves per SIMD): with tiles of
 // up to 7 periods, 8 workgroups then fit a CU's LDS and registers alike.
 template <bool WEIGHTED, bool DIP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEIGHTED ? 1 : 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEIGHTED ? 6 : 8)))
 void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
   __shared__ double s_f[kTileMax];
