@@ -1440,6 +1440,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   __shared__ int s_curve;
   __shared__ int s_per;
   __shared__ unsigned long long s_vbits;
+  __shared__ unsigned long long s_theta;
   __shared__ unsigned int s_tie;
   __shared__ long long s_bestS, s_bestR;
   __shared__ long long s_wsum[kBlock / 64];
@@ -1499,6 +1500,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     for (int i = tid; i <= M; i += kBlock) cnt[i] = 0;
     if (tid == 0) {
       s_vbits = 0ull;
+      s_theta = 0ull;
       s_tie = 0xFFFFFFFFu;
     }
     __syncthreads();
@@ -1579,17 +1581,27 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
 
     // Runs from every start position.  Four run steps per iteration: their
     // points and phases are loaded together, then the steps are taken in
-    // order with the same stop rules.  Candidates are compared without a
-    // division (S^2 / den against the lane's best as cross products); the
-    // lane's best value is divided out once at the end.
+    // order with the same stop rules.  S and R are summed in FP64, which is
+    // exact here (|q|, w < 2^30 and at most kUnbinnedMaxPoints points keep
+    // every partial sum below 2^53).  Each step is screened against theta,
+    // the best value any lane of the workgroup has found so far in this
+    // period (s_theta, raised as lanes improve; the lanes' final bests go to
+    // s_vbits as before): a run with
+    // S^2 < theta (1 - 2^-20) R (W - R) can be neither the best nor a tie
+    // of it, so it skips the admissibility tests and the exact comparison.
+    // Candidates are compared without a division (S^2 / den against the
+    // lane's best as cross products).
     double bnum = 0.0, bden = 1.0;
     unsigned int btie = 0xFFFFFFFFu;
-    long long bS = 0, bR = 0;
+    double bS = 0.0, bR = 0.0;
     for (int r = tid; r < nk; r += kBlock) {
       const int prev = r == 0 ? nk - 1 : r - 1;
       const double ph_r = sph[r], ph_prev = sph[prev];
       if (!(fwd_phase(ph_prev, ph_r, prev, r) > 0.0)) continue;
-      long long S = 0, R = 0;
+      const unsigned long long tb =
+          __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      double thr = __longlong_as_double((long long)tb) * (1.0 - 0x1p-20);
+      double S = 0.0, R = 0.0;
       int last = r;
       bool go = true;
       for (int len = 1; go && len <= nk - 1; len += 4) {
@@ -1613,24 +1625,23 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
             go = false;
             break;
           }
-          S += qv[u];
-          R += wv[u];
+          S += (double)qv[u];
+          R += WEIGHTED ? (double)wv[u] : 1.0;
           const double span = L == 1 ? 0.0 : fwd_phase(ph_r, ph[u], r, idx[u]);
           if (!(span < qhi)) {
             go = false;
             break;
           }
+          if (DIP && !(S < 0.0)) continue;
+          const double den = R * (Wd - R);
+          const double num = S * S;
+          if (num < thr * den) continue;
           const int next = idx[u + 1];
           if (!(fwd_phase(ph[u], ph[u + 1], idx[u], next) > 0.0)) continue;
           const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, ph[u + 1], prev, next);
           if (!(gap > qlo)) continue;
           if (L < a.min_in_points) continue;
-          if (DIP && !(S < 0)) continue;
-          const double Rd = (double)R;
-          const double den = Rd * (Wd - Rd);
-          if (!(den > 0.0) || S == 0) continue;
-          const double Sd = (double)S;
-          const double num = Sd * Sd;
+          if (!(den > 0.0) || S == 0.0) continue;
           const double lhs = num * bden, rhs = bnum * den;
           const unsigned int tie = (unsigned)L * (unsigned)nk + (unsigned)r;
           if (lhs > rhs || (lhs == rhs && tie < btie)) {
@@ -1639,6 +1650,10 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
             btie = tie;
             bS = S;
             bR = R;
+            const double v = num / den;
+            thr = fmax(thr, v * (1.0 - 0x1p-20));
+            __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(v),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
         last = idx[4];
@@ -1651,8 +1666,8 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     if (bv > 0.0 && vb == s_vbits) atomicMin(&s_tie, btie);
     __syncthreads();
     if (bv > 0.0 && vb == s_vbits && btie == s_tie) {
-      s_bestS = bS;
-      s_bestR = bR;
+      s_bestS = (long long)bS;  // exact integers
+      s_bestR = (long long)bR;
     }
     __syncthreads();
     if (tid == 0) {
