@@ -1579,9 +1579,9 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     const double Wd = (double)W;
     const double qlo = cd.qlo, qhi = cd.qhi;
 
-    // Runs from every start position.  Four run steps per iteration: their
-    // points and phases are loaded together, then the steps are taken in
-    // order with the same stop rules.  S and R are summed in FP64, which is
+    // Runs from every start position, four run steps per iteration with
+    // their values loaded together, up to the longest run a box shorter than
+    // qhi in phase can hold.  S and R are summed in FP64, which is
     // exact here (|q|, w < 2^30 and at most kUnbinnedMaxPoints points keep
     // every partial sum below 2^53).  Each step is screened against theta,
     // the best value any lane of the workgroup has found so far in this
@@ -1601,44 +1601,51 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       const unsigned long long tb =
           __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       double thr = __longlong_as_double((long long)tb) * (1.0 - 0x1p-20);
+      // Longest run from r that a box with duty cycle below qhi can hold:
+      // the span from r grows along the phase order, so it is found by
+      // bisection (a run of one point spans nothing).
+      int lmax = 1;
+      {
+        int hi = nk - 1;
+        while (lmax < hi) {
+          const int mid = (lmax + hi + 1) >> 1;
+          int e = r + mid - 1;
+          if (e >= nk) e -= nk;
+          if (fwd_phase(ph_r, sph[e], r, e) < qhi)
+            lmax = mid;
+          else
+            hi = mid - 1;
+        }
+      }
       double S = 0.0, R = 0.0;
-      int last = r;
-      bool go = true;
-      for (int len = 1; go && len <= nk - 1; len += 4) {
-        int idx[5];
-        idx[0] = last;
+      int e0 = r;  // first position of the next group of four
+      for (int len = 1; len <= lmax; len += 4) {
+        int idx[4];
+        idx[0] = e0;
 #pragma unroll
-        for (int u = 1; u < 5; ++u) idx[u] = idx[u - 1] + 1 == nk ? 0 : idx[u - 1] + 1;
+        for (int u = 1; u < 4; ++u) idx[u] = idx[u - 1] + 1 == nk ? 0 : idx[u - 1] + 1;
         int qv[4], wv[4];
-        double ph[5];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           qv[u] = sq[idx[u]];
           wv[u] = WEIGHTED ? sw[idx[u]] : 1;
-          ph[u] = sph[idx[u]];
         }
-        ph[4] = sph[idx[4]];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int L = len + u;
-          if (L > nk - 1) {
-            go = false;
-            break;
-          }
+          if (L > lmax) break;
           S += (double)qv[u];
           R += WEIGHTED ? (double)wv[u] : 1.0;
-          const double span = L == 1 ? 0.0 : fwd_phase(ph_r, ph[u], r, idx[u]);
-          if (!(span < qhi)) {
-            go = false;
-            break;
-          }
           if (DIP && !(S < 0.0)) continue;
           const double den = R * (Wd - R);
           const double num = S * S;
           if (num < thr * den) continue;
-          const int next = idx[u + 1];
-          if (!(fwd_phase(ph[u], ph[u + 1], idx[u], next) > 0.0)) continue;
-          const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, ph[u + 1], prev, next);
+          // Rare: the run passed the screen; its edges must be admissible.
+          const int e = idx[u];
+          const int next = e + 1 == nk ? 0 : e + 1;
+          const double pe = sph[e], pn = sph[next];
+          if (!(fwd_phase(pe, pn, e, next) > 0.0)) continue;
+          const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, pn, prev, next);
           if (!(gap > qlo)) continue;
           if (L < a.min_in_points) continue;
           if (!(den > 0.0) || S == 0.0) continue;
@@ -1656,7 +1663,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
-        last = idx[4];
+        e0 = idx[3] + 1 == nk ? 0 : idx[3] + 1;
       }
     }
     const double bv = bnum > 0.0 ? bnum / bden : 0.0;
