@@ -85,6 +85,23 @@ def test_sparse_bins_empty_boxes(bls, plan, n, nbins, dip):
     check_curve(lc, g, _orc(lc, dip_only=dip), label="sparse%d" % n)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_dense_cadence_lane_gap(bls, plan, weighted):
+    """A 1-minute cadence with long trial periods: the fold spaces its lanes
+    2 and 4 runs of points apart in full chunks of 1024 points (the lane gap
+    follows the curve's cadence), which must not change any bin sum."""
+    rng = np.random.default_rng(91)
+    n = 5000
+    t = synth.minute_grid_times(n)
+    x = 1.0 + rng.normal(0.0, 0.003, n)
+    x -= 0.01 * (((t - t[0]) % 7.3) < 0.15)        # a box at 7.3 d
+    w = rng.uniform(0.5, 2.0, n) if weighted else None
+    per = synth.log_period_grid(2.0, 20.0, 48)
+    lc = synth.LightCurve(t, x, w, per, 1000, 0.005, 0.05)
+    _say("dense cadence lane gap", n, weighted)
+    check_curve(lc, _run(bls, plan, lc), _orc(lc), label="dense%d" % weighted)
+
+
 def test_single_period_and_widest_boxes(bls, plan):
     lc = synth.small_curve(5, 400, nperiods=1, nbins=50, qmin=0.01,
                            qmax=0.999)
