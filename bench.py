@@ -541,8 +541,14 @@ def suite_detect(args, bls):
             kms.append(bls.bls_last_stats(p.handle)["search_ms"])
     k_ms = _median(kms[1:])
     m = float(b.ncurves) * b.periods.size
-    # one pass for the mean, one for the deviation and maximum, one per peak
-    nbytes = 4.0 * m * (2 + 8) + 8.0 * b.periods.size * 8
+    # algorithmic bytes: every SR value once, the shared period grid once and
+    # one detection record per curve (the kernel itself makes ten passes over
+    # a curve's SR values: the mean, the deviation, one per peak)
+    import ctypes
+
+    from paper_1112_1701_amd import _lib
+    nbytes = (4.0 * m + 8.0 * b.periods.size +
+              float(b.ncurves) * ctypes.sizeof(_lib.BlsDetection))
     achieved = nbytes / (k_ms * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:
