@@ -542,8 +542,8 @@ def suite_detect(args, bls):
     k_ms = _median(kms[1:])
     m = float(b.ncurves) * b.periods.size
     # algorithmic bytes: every SR value once, the shared period grid once and
-    # one detection record per curve (the kernel itself makes ten passes over
-    # a curve's SR values: the mean, the deviation, one per peak)
+    # one detection record per curve (the kernel reads a curve's SR values
+    # twice, for the mean and then the deviation, plus rare refills)
     import ctypes
 
     from paper_1112_1701_amd import _lib

@@ -245,7 +245,7 @@ int bls_search_unbinned_device(bls_plan *plan, const bls_batch *batch,
  * batch: as for bls_search_device (periods are device pointers); sr: device
  * [results] as written by bls_search_device for that batch.  out: host
  * [ncurves].  Synchronous on the plan's stream.  Errors: INVALID_ARG,
- * CAPACITY (a curve with more than 2^20 periods), DEVICE.
+ * CAPACITY, DEVICE.
  */
 #define BLS_MAX_PEAKS 16
 typedef struct {

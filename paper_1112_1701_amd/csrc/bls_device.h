@@ -127,7 +127,6 @@ struct DetectArgs {
   int32_t max_peaks;
   double window;
   double threshold;
-  int32_t mask_words;  // LDS bitmask words (>= max nperiods / 32)
 };
 
 // Eclipse detection efficiency of an observing cadence (window function).

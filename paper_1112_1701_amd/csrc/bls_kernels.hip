@@ -891,13 +891,32 @@ __global__ void bins_kernel(const double *dt, int64_t n, const double *period, i
 
 // ------------------------------------------------------------- detection
 // One workgroup per curve: mean and population deviation of SR (FP64), then
-// peaks largest first with neighbourhood / harmonic suppression tracked in
-// an LDS bitmask.
+// peaks largest first, a peak at P suppressing every P' within
+// window * hP of hP for h in {1, 1/2, 2, 1/3, 3}.
+//
+// Peaks without a pass per peak: while the deviation pass reads SR, every
+// thread keeps the kDetList largest keys of its slice of periods (p = tid +
+// kBlock j, positive SR only) with their periods.  A key is (SR bits, ~p),
+// unique, and orders periods as the peaks are chosen (larger SR, then the
+// smaller index).  For each peak a thread offers its largest entry not yet
+// suppressed, the workgroup takes the largest offer, and every thread tests
+// its remaining entries against the new peak.  A thread whose entries are all
+// used up while its slice holds more positive values scans its slice again
+// against every peak so far and refills its list.
+// List length: each entry costs four VGPRs and insertion work in the
+// deviation pass; too short a list runs out near strong peaks and their
+// harmonics, and a refill re-reads the slice.  On 20000-period periodograms
+// of 2000-point curves, 12 is fastest for 8 peaks (8: refills set the
+// kernel's tail; 16: the pass loses occupancy).
+constexpr int kDetList = 12;
+constexpr int kDetBatch = 8;   // loads in flight per pass
+constexpr int kDetRefill = 4;  // loads in flight per refill (registers)
+
 __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
-  extern __shared__ unsigned int s_mask[];
   __shared__ double sa[kBlock];
   __shared__ double sb[kBlock];
-  __shared__ unsigned long long s_key;
+  __shared__ unsigned long long s_key[kBlock / 64];  // one offer per wave
+  __shared__ double s_peak[BLS_MAX_PEAKS];
   const int c = blockIdx.x;
   if (c >= a.ncurves) return;
   const DetectDesc dd = a.desc[c];
@@ -907,63 +926,187 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   bls_detection *out = reinterpret_cast<bls_detection *>(a.out) + c;
   const int tid = threadIdx.x;
 
+  // Both passes keep kDetBatch loads of the thread's slice in flight (whole
+  // batches first, then the tail); values are still taken in index order,
+  // one slice per thread.
+  const int64_t full = m - (int64_t)(kDetBatch - 1) * kBlock;  // p0 < full: whole batch
   double sum = 0.0, mx = 0.0;
-  for (int64_t p = tid; p < m; p += kBlock) sum = sum + (double)sr[p];
+  int64_t p0 = tid;
+  for (; p0 < full; p0 += kDetBatch * kBlock) {
+    float v[kDetBatch];
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) v[u] = sr[p0 + (int64_t)u * kBlock];
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) sum = sum + (double)v[u];
+  }
+  for (int64_t p = p0; p < m; p += kBlock) sum = sum + (double)sr[p];
   double dummy = 0.0;
   block_sum2(sum, dummy, sa, sb);
   const double mean = sum / (double)m;
+
+  // Deviation pass, which also fills this thread's list (descending keys).
+  unsigned long long top[kDetList];
+#pragma unroll
+  for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
+  int npos = 0;  // positive SR values in this thread's slice
   double ss = 0.0;
   mx = -INFINITY;
-  for (int64_t p = tid; p < m; p += kBlock) {
-    const double dv = (double)sr[p] - mean;
+  auto take = [&](float v, int64_t p) {
+    const double dv = (double)v - mean;
     ss = ss + dv * dv;
-    mx = fmax(mx, (double)sr[p]);
+    mx = fmax(mx, (double)v);
+    if (v > 0.0f) {
+      ++npos;
+      unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                               (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+      if (key > top[kDetList - 1]) {
+#pragma unroll
+        for (int i = 0; i < kDetList; ++i) {
+          if (key > top[i]) {
+            const unsigned long long o = top[i];
+            top[i] = key;
+            key = o;
+          }
+        }
+      }
+    }
+  };
+  for (p0 = tid; p0 < full; p0 += kDetBatch * kBlock) {
+    float v[kDetBatch];
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) v[u] = sr[p0 + (int64_t)u * kBlock];
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) take(v[u], p0 + (int64_t)u * kBlock);
   }
+  for (int64_t p = p0; p < m; p += kBlock) take(sr[p], p);
   block_sum2(ss, dummy, sa, sb);
   double mn = INFINITY;
   block_minmax(mn, mx, sa, sb);
   const double sd = sqrt(ss / (double)m);
   const double sde = sd > 0.0 ? (mx - mean) / sd : 0.0;
 
-  for (int i = tid; i < a.mask_words; i += kBlock) s_mask[i] = 0u;
-  __syncthreads();
+  auto key_index = [](unsigned long long key) -> int64_t {
+    return (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+  };
+  double tper[kDetList];
+  unsigned dead = 0u;  // bit i: entry i empty, taken or suppressed
+#pragma unroll
+  for (int i = 0; i < kDetList; ++i) {
+    tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
+    if (!top[i]) dead |= 1u << i;
+  }
+  bool more = npos > kDetList;  // the slice holds values the list dropped
   const double harm[5] = {1.0, 0.5, 2.0, 1.0 / 3.0, 3.0};
+  auto suppressed = [&](double Pp, double P) {
+    bool off = false;
+    for (int h = 0; h < 5; ++h) {
+      const double cp = harm[h] * P;
+      if (fabs(Pp - cp) <= a.window * cp) off = true;
+    }
+    return off;
+  };
+
   int k = 0;
   for (; k < a.max_peaks; ++k) {
-    if (tid == 0) s_key = 0ull;
-    __syncthreads();
-    unsigned long long best = 0ull;
-    for (int64_t p = tid; p < m; p += kBlock) {
-      const float v = sr[p];
-      if (v > 0.0f && !(s_mask[p >> 5] & (1u << (p & 31)))) {
-        const unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                                       (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-        best = key > best ? key : best;
+    if (dead == (1u << kDetList) - 1u && more) {
+      // Refill the list with the slice's largest entries free of every peak
+      // so far.  Only a value that would enter the list is tested; one that
+      // would not, or one pushed out, leaves `more` set (a later refill
+      // tests it then).
+#pragma unroll
+      for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
+      more = false;
+      auto retake = [&](float v, double Pp, int64_t p) {
+        if (!(v > 0.0f)) return;
+        unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
+                                 (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+        if (key < top[kDetList - 1]) {
+          more = true;
+          return;
+        }
+        bool off = false;
+        for (int j = 0; j < k; ++j) off = off || suppressed(Pp, s_peak[j]);
+        if (off) return;
+        if (top[kDetList - 1]) more = true;  // the last entry drops out
+#pragma unroll
+        for (int i = 0; i < kDetList; ++i) {
+          if (key > top[i]) {
+            const unsigned long long o = top[i];
+            top[i] = key;
+            key = o;
+          }
+        }
+      };
+      // Loads in batches, as in the passes above: a refill is a chain of
+      // dependent loads otherwise.
+      const int64_t rfull = m - (int64_t)(kDetRefill - 1) * kBlock;
+      int64_t q0 = tid;
+      for (; q0 < rfull; q0 += kDetRefill * kBlock) {
+        float v[kDetRefill];
+        double pp[kDetRefill];
+#pragma unroll
+        for (int u = 0; u < kDetRefill; ++u) {
+          v[u] = sr[q0 + (int64_t)u * kBlock];
+          pp[u] = per[q0 + (int64_t)u * kBlock];
+        }
+#pragma unroll
+        for (int u = 0; u < kDetRefill; ++u) retake(v[u], pp[u], q0 + (int64_t)u * kBlock);
+      }
+      for (int64_t q = q0; q < m; q += kBlock) retake(sr[q], per[q], q);
+      dead = 0u;
+#pragma unroll
+      for (int i = 0; i < kDetList; ++i) {
+        tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
+        if (!top[i]) dead |= 1u << i;
       }
     }
-    if (best) __hip_atomic_fetch_max(&s_key, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    unsigned long long offer = 0ull;
+    int mine = -1;
+#pragma unroll
+    for (int i = kDetList - 1; i >= 0; --i)
+      if (!((dead >> i) & 1u)) {
+        offer = top[i];
+        mine = i;
+      }
+    // Largest offer: across the wave by shuffles, across the waves in LDS.
+    // (Every read of s_key for the previous peak happened before the barrier
+    // that published that peak's period.)
+    unsigned long long wbest = offer;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long x = __shfl_xor(wbest, o);
+      wbest = x > wbest ? x : wbest;
+    }
+    if ((tid & 63) == 0) s_key[tid >> 6] = wbest;
     __syncthreads();
-    const unsigned long long key = s_key;
+    unsigned long long key = s_key[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
     if (key == 0ull) break;
-    const int64_t pk = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+    if (offer == key) {  // the owner: its entry's period for everyone
+#pragma unroll
+      for (int i = 0; i < kDetList; ++i)
+        if (i == mine) s_peak[k] = tper[i];
+    }
+    __syncthreads();
+    const double P = s_peak[k];
+    const int64_t pk = key_index(key);
     const float vk = __uint_as_float((unsigned)(key >> 32));
     if (tid == 0) {
       out->peak_index[k] = pk;
       out->peak_sr[k] = vk;
       out->peak_sde[k] = sd > 0.0 ? (float)(((double)vk - mean) / sd) : 0.0f;
     }
-    const double P = per[pk];
-    for (int64_t p = tid; p < m; p += kBlock) {
-      bool off = false;
-      for (int h = 0; h < 5; ++h) {
-        const double cp = harm[h] * P;
-        if (fabs(per[p] - cp) <= a.window * cp) off = true;
-      }
-      if (off)
-        __hip_atomic_fetch_or(&s_mask[p >> 5], 1u << (p & 31), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    // The suppression test of every entry, harmonic by harmonic (the same
+    // products as the refill's test, so the two agree bit for bit).
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+      const double cp = harm[h] * P;
+      const double wc = a.window * cp;
+#pragma unroll
+      for (int i = 0; i < kDetList; ++i)
+        if (fabs(tper[i] - cp) <= wc) dead |= 1u << i;
     }
-    __syncthreads();
   }
   if (tid == 0) {
     out->mean_sr = mean;
@@ -1778,11 +1921,7 @@ int launch_bins(const double *dt, int64_t n, const double *period, int32_t nbins
 
 int launch_detect(const DetectArgs &a, void *stream) {
   if (a.ncurves <= 0) return 0;
-  const size_t lds = (size_t)a.mask_words * 4;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&detect_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(detect_kernel, dim3(a.ncurves), dim3(kBlock), lds, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(detect_kernel, dim3(a.ncurves), dim3(kBlock), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

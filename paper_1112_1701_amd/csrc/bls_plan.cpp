@@ -979,15 +979,11 @@ int bls_detect_device(bls_plan *p, const bls_batch *b, const float *sr, int32_t 
   if (e != hipSuccess) return hip_error(p, e, "set device");
   const int nc = b->ncurves;
   std::vector<DetectDesc> dd(nc);
-  int64_t mmax = 0;
   for (int c = 0; c < nc; ++c) {
     dd[c].p_off = shapes[c].p_off;
     dd[c].r_off = shapes[c].r_off;
     dd[c].nperiods = shapes[c].nperiods;
-    mmax = std::max<int64_t>(mmax, shapes[c].nperiods);
   }
-  if (mmax > (int64_t(1) << 20))
-    return set_error(p, BLS_ERR_CAPACITY, "detection handles at most 2^20 periods per curve");
   if (!p->d_detect_desc) {
     if ((e = device_alloc((void **)&p->d_detect_desc, sizeof(DetectDesc) * p->cfg.max_curves)) ||
         (e = device_alloc((void **)&p->d_detect_out, sizeof(bls_detection) * p->cfg.max_curves))) {
@@ -1010,7 +1006,6 @@ int bls_detect_device(bls_plan *p, const bls_batch *b, const float *sr, int32_t 
   a.max_peaks = max_peaks;
   a.window = window;
   a.threshold = sde_threshold;
-  a.mask_words = (int32_t)std::max<int64_t>(1, (mmax + 31) / 32);
   if ((e = hipEventRecord(p->ev_search0, s)) != hipSuccess) return hip_error(p, e, "event");
   if ((e = (hipError_t)launch_detect(a, s))) return hip_error(p, e, "launch detection");
   if ((e = hipEventRecord(p->ev_search1, s)) != hipSuccess) return hip_error(p, e, "event");

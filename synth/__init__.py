@@ -23,4 +23,5 @@ from .lightcurves import (  # noqa: F401
     survey_cadence,
     cadence_batch,
     variability_field,
+    detection_periodograms,
 )

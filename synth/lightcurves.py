@@ -370,3 +370,49 @@ def variability_field(nstars: int = 100000, nchips: int = 11,
               np.full(nstars, 2, np.int32), np.full(nstars, 0.1),
               np.full(nstars, 0.1))
     return b, mag, chip_off, var
+
+
+def detection_periodograms(seed: int = _BASE_SEED + 9):
+    """Crafted periodograms for the detection step: a list of (SR, periods,
+    max_peaks, window).  Strides of 256 match the slices one workgroup's
+    threads take, so the cases reach the corners of a parallel peak search:
+    the largest values crowded into one slice, suppression across slices,
+    ties, an early stop, fewer periods than threads."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    # The 24 largest values all in one 256-stride slice (indices 3 mod 256):
+    # more than a thread keeps of its slice, so 16 peaks force a refill.
+    m = 256 * 30 + 17
+    sr = rng.uniform(0.0, 1.0, m)
+    sr[3 + 256 * np.arange(24)] = 2.0 + rng.uniform(0.0, 1.0, 24)
+    cases.append((sr, np.geomspace(1.0, 40.0, m), 16, 1e-6))
+    # Same slice, but its peaks are wiped out by harmonics of a peak elsewhere:
+    # suppression across slices, then refills.
+    per = np.geomspace(0.5, 40.0, m)
+    sr = rng.uniform(0.0, 1.0, m)
+    top = 5 + 256 * np.arange(20)
+    sr[top] = 2.0 + rng.uniform(0.0, 1.0, 20)
+    j = int(np.argmin(np.abs(per - 2.0 * per[top[4]])))
+    sr[j] = 9.0
+    cases.append((sr, per, 16, 0.05))
+    # Heavy ties: few distinct values, the smallest index must win each tie.
+    m = 256 * 12 + 200
+    sr = np.round(rng.uniform(0.0, 1.0, m) * 3.0) / 3.0
+    cases.append((sr, np.linspace(1.0, 30.0, m), 16, 0.002))
+    # A wide window: every peak suppresses large stretches, every slice
+    # empties its list many times.
+    sr = rng.gamma(2.0, 1.0, m)
+    cases.append((sr, np.linspace(0.3, 30.0, m), 16, 0.3))
+    # Few positive values (zeros and negatives otherwise): the search stops
+    # early; npeaks < max_peaks.
+    sr = np.zeros(m)
+    sr[rng.choice(m, 5, replace=False)] = rng.uniform(0.1, 1.0, 5)
+    sr[rng.choice(m, 50, replace=False)] = -0.5
+    cases.append((sr, np.linspace(1.0, 30.0, m), 16, 0.0))
+    # Fewer periods than threads, a single period, a slice of exactly 9.
+    for mm in (1, 7, 255, 256 * 9):
+        cases.append((rng.uniform(0.0, 1.0, mm), np.linspace(1.0, 9.0, mm),
+                      16, 0.01))
+    # All SR equal and positive: std 0, sde 0, peaks by index only.
+    cases.append((np.full(700, 0.25), np.linspace(1.0, 2.0, 700), 5, 0.0))
+    return cases

@@ -374,6 +374,44 @@ def test_detection_statistics(bls):
             oo.sr >= (1 - 1e-5) * oo.sr.max())
 
 
+def test_detection_crafted_periodograms(bls):
+    """GPU detection of crafted SR arrays (float32, as the search writes
+    them) equals the oracle's detection of the same values: peak indices
+    bit-exact, statistics to FP64 rounding.  The cases drive the kernel's
+    candidate lists through refills, cross-slice suppression, ties and the
+    early stop."""
+    import torch
+    cases = synth.detection_periodograms()
+    dev = torch.device("cuda:0")
+    nc = len(cases)
+    _say("detection crafted", nc)
+    srs = [np.asarray(c[0], np.float32) for c in cases]
+    p_off = np.concatenate([[0], np.cumsum([s.size for s in srs])])
+    per = torch.tensor(np.concatenate([c[1] for c in cases]), device=dev)
+    srd = torch.tensor(np.concatenate(srs), device=dev)
+    n_off = np.arange(nc + 1, dtype=np.int64) * 4
+    with bls.Plan(max_curves=nc, max_points=1 << 12, max_periods=1 << 16) as p:
+        for mp, win in sorted({(c[2], c[3]) for c in cases}):
+            det = bls.bls_detect_device(p.handle, n_off, per, p_off, 200,
+                                        0.01, 0.1, srd, max_peaks=mp,
+                                        window=win, sde_threshold=3.0)
+            for c, case in enumerate(cases):
+                if (case[2], case[3]) != (mp, win):
+                    continue
+                o = oracle.detect(srs[c].astype(np.float64), case[1],
+                                  max_peaks=mp, window=win, threshold=3.0)
+                g = det[c]
+                assert np.array_equal(g["peak_index"], o["peak_index"]), \
+                    (c, g["peak_index"], o["peak_index"])
+                assert np.array_equal(g["peak_sr"].astype(np.float64),
+                                      o["peak_sr"]), c
+                for k in ("mean", "std", "sde"):
+                    gv = g[k if k == "sde" else k + "_sr"]
+                    assert abs(gv - o[k]) <= 1e-12 * max(abs(o[k]), 1e-30), \
+                        (c, k, gv, o[k])
+                assert g["candidate"] == o["candidate"], c
+
+
 def test_single_bin_boxes(bls, plan):
     """kmax = 1 (20 bins, q up to 0.05): each period's histogram is its bins
     plus one clamp word, so the LDS tile must hold nbins + 1 words per

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 
 def test_closed_form_small_case():
@@ -76,3 +77,17 @@ def test_sde_affine_invariance(a, c):
     d2 = oracle.detect(a * sr + c, per, max_peaks=3)
     assert abs(d1["sde"] - d2["sde"]) < 1e-9
     assert d1["peak_index"].tolist() == d2["peak_index"].tolist()
+
+
+def test_crafted_refill_case_crowds_one_slice():
+    """The first crafted detection case is what it claims: all 16 peaks
+    (the 24 raised values, window too small to suppress) sit at indices
+    3 mod 256, one thread slice of a 256-wide workgroup."""
+    sr, per, mp, win = synth.detection_periodograms()[0]
+    o = oracle.detect(np.asarray(sr, np.float32).astype(np.float64), per,
+                      max_peaks=mp, window=win)
+    assert o["peak_index"].size == 16
+    assert np.all(o["peak_index"] % 256 == 3)
+    # Largest first among the raised values.
+    raised = np.sort(np.asarray(sr, np.float32)[3 + 256 * np.arange(24)])
+    assert np.array_equal(o["peak_sr"], raised[::-1][:16].astype(np.float64))
