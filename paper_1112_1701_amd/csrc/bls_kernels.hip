@@ -1265,9 +1265,14 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
 
     // Scan: one task per (period, offset), windows of k bins.
     const int need2 = a.min_eclipses >= 2;
+    // Tasks tid, tid + kBlock, ... as (period t, offset j), stepped without
+    // a division (nb >= 2, so one subtraction may not suffice: loop).
+    int t = 0, j = tid;
+    while (j >= nb) {
+      j -= nb;
+      ++t;
+    }
     for (int task = tid; task < np * nb; task += kBlock) {
-      const int t = task / nb;
-      const int j = task - t * nb;
       const int k = s_k[t];
       const int2 *h = s_mm + t * nb;
       // The window is decided as soon as it holds the required eclipses:
@@ -1308,6 +1313,11 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
         if ((int)(threadIdx.x & 63) == lead && (hit & same))
           atomicAdd(&s_count[tl], __popcll(hit & same));
         pending &= ~same;
+      }
+      j += kBlock;
+      while (j >= nb) {
+        j -= nb;
+        ++t;
       }
     }
     __syncthreads();
