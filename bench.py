@@ -543,7 +543,7 @@ def suite_detect(args, bls):
     m = float(b.ncurves) * b.periods.size
     # algorithmic bytes: every SR value once, the shared period grid once and
     # one detection record per curve (the kernel reads a curve's SR values
-    # twice, for the mean and then the deviation, plus rare refills)
+    # once, plus a thread's slice again on a rare refill)
     import ctypes
 
     from paper_1112_1701_amd import _lib

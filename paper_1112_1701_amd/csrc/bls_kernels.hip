@@ -47,6 +47,42 @@ __device__ inline void block_sum2(double &a, double &b, double *sa, double *sb) 
   __syncthreads();
 }
 
+// Count, mean and sum of squared deviations of the workgroup's values from
+// each thread's own (n, mean, m2), merged pairwise in a fixed tree (the
+// update of Chan, Golub and LeVeque); threads without values hold n = 0.
+__device__ inline void block_chan(double &n, double &mean, double &m2, double *sa, double *sb,
+                                  double *sc) {
+  const int tid = threadIdx.x;
+  sa[tid] = n;
+  sb[tid] = mean;
+  sc[tid] = m2;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double na = sa[tid], nb = sa[tid + s];
+      if (nb > 0.0) {
+        if (na > 0.0) {
+          const double nn = na + nb;
+          const double delta = sb[tid + s] - sb[tid];
+          const double fb = nb / nn;
+          sb[tid] = sb[tid] + delta * fb;
+          sc[tid] = sc[tid] + sc[tid + s] + delta * delta * na * fb;
+          sa[tid] = nn;
+        } else {
+          sa[tid] = nb;
+          sb[tid] = sb[tid + s];
+          sc[tid] = sc[tid + s];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  n = sa[0];
+  mean = sb[0];
+  m2 = sc[0];
+  __syncthreads();
+}
+
 __device__ inline void block_minmax(double &mn, double &mx, double *sa, double *sb) {
   const int tid = threadIdx.x;
   sa[tid] = mn;
@@ -915,6 +951,7 @@ constexpr int kDetRefill = 4;  // loads in flight per refill (registers)
 __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   __shared__ double sa[kBlock];
   __shared__ double sb[kBlock];
+  __shared__ double sc[kBlock];
   __shared__ unsigned long long s_key[kBlock / 64];  // one offer per wave
   __shared__ double s_peak[BLS_MAX_PEAKS];
   const int c = blockIdx.x;
@@ -926,34 +963,18 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   bls_detection *out = reinterpret_cast<bls_detection *>(a.out) + c;
   const int tid = threadIdx.x;
 
-  // Both passes keep kDetBatch loads of the thread's slice in flight (whole
-  // batches first, then the tail); values are still taken in index order,
-  // one slice per thread.
-  const int64_t full = m - (int64_t)(kDetBatch - 1) * kBlock;  // p0 < full: whole batch
-  double sum = 0.0, mx = 0.0;
-  int64_t p0 = tid;
-  for (; p0 < full; p0 += kDetBatch * kBlock) {
-    float v[kDetBatch];
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) v[u] = sr[p0 + (int64_t)u * kBlock];
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) sum = sum + (double)v[u];
-  }
-  for (int64_t p = p0; p < m; p += kBlock) sum = sum + (double)sr[p];
-  double dummy = 0.0;
-  block_sum2(sum, dummy, sa, sb);
-  const double mean = sum / (double)m;
-
-  // Deviation pass, which also fills this thread's list (descending keys).
+  // One pass over SR.  A thread reads its slice kDetBatch values at a time
+  // (whole batches, then the tail) and keeps: the running count, mean and sum
+  // of squared deviations of its values, each batch merged in by the pairwise
+  // update of Chan, Golub and LeVeque (one value at a time in the tail); its
+  // largest value; and its list (descending keys).  The workgroup merges the
+  // threads' statistics the same way, in a fixed tree.
   unsigned long long top[kDetList];
 #pragma unroll
   for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
   int npos = 0;  // positive SR values in this thread's slice
-  double ss = 0.0;
-  mx = -INFINITY;
+  double cn = 0.0, cmean = 0.0, cm2 = 0.0, mx = -INFINITY;
   auto take = [&](float v, int64_t p) {
-    const double dv = (double)v - mean;
-    ss = ss + dv * dv;
     mx = fmax(mx, (double)v);
     if (v > 0.0f) {
       ++npos;
@@ -971,18 +992,44 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
       }
     }
   };
-  for (p0 = tid; p0 < full; p0 += kDetBatch * kBlock) {
+  const int64_t full = m - (int64_t)(kDetBatch - 1) * kBlock;  // p0 < full: whole batch
+  int64_t p0 = tid;
+  for (; p0 < full; p0 += kDetBatch * kBlock) {
     float v[kDetBatch];
 #pragma unroll
     for (int u = 0; u < kDetBatch; ++u) v[u] = sr[p0 + (int64_t)u * kBlock];
+    double bs = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) bs = bs + (double)v[u];
+    const double bmean = bs * (1.0 / kDetBatch);  // exact: a power of two
+    double bm2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u) {
+      const double dv = (double)v[u] - bmean;
+      bm2 = bm2 + dv * dv;
+    }
+    const double nn = cn + (double)kDetBatch;
+    const double delta = bmean - cmean;
+    const double fb = (double)kDetBatch / nn;
+    cmean = cmean + delta * fb;
+    cm2 = cm2 + bm2 + delta * delta * cn * fb;
+    cn = nn;
 #pragma unroll
     for (int u = 0; u < kDetBatch; ++u) take(v[u], p0 + (int64_t)u * kBlock);
   }
-  for (int64_t p = p0; p < m; p += kBlock) take(sr[p], p);
-  block_sum2(ss, dummy, sa, sb);
+  for (int64_t p = p0; p < m; p += kBlock) {
+    const float v = sr[p];
+    cn = cn + 1.0;
+    const double delta = (double)v - cmean;
+    cmean = cmean + delta / cn;
+    cm2 = cm2 + delta * ((double)v - cmean);
+    take(v, p);
+  }
+  block_chan(cn, cmean, cm2, sa, sb, sc);
   double mn = INFINITY;
   block_minmax(mn, mx, sa, sb);
-  const double sd = sqrt(ss / (double)m);
+  const double mean = cmean;
+  const double sd = sqrt(cm2 / (double)m);
   const double sde = sd > 0.0 ? (mx - mean) / sd : 0.0;
 
   auto key_index = [](unsigned long long key) -> int64_t {
