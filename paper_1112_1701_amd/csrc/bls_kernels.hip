@@ -14,6 +14,19 @@
 //   fill_kernel / best_index_kernel  counter and per-curve key set-up and
 //                   read-out (plain kernels so that the sequence can be
 //                   captured in a HIP graph)
+//   unbinned_kernel box edges between points: per (curve, period) item the
+//                   phases ordered in LDS and every run of consecutive points
+//                   scored with exact sums
+//   detect_kernel   one workgroup per periodogram: SR statistics in one pass
+//                   and the strongest peaks with harmonic suppression, taken
+//                   from per-thread candidate lists
+//   window_prep_kernel / window_kernel  eclipse detection efficiency of a
+//                   cadence: per (cadence, period tile) the smallest and
+//                   largest cycle in each phase bin, then one decision per
+//                   trial eclipse epoch
+//   var_rms_kernel / var_clip_kernel  high-variability pre-search: per-star
+//                   RMS, then per (chip, magnitude bin) clipped statistics
+//                   and the flagged stars
 //
 // No FP contraction anywhere (-ffp-contract=off): the phase is computed with
 // exactly the FP64 operation sequence of its definition so that every point
@@ -1618,8 +1631,8 @@ __global__ __launch_bounds__(kBlock) void var_clip_kernel(VarArgs a) {
 // cycle in [qlo, qhi] holds exactly is scored.  The order is found without a
 // comparison sort: a counting sort on a fine phase grid (about one point per
 // cell) groups the points, and each point's rank is its cell's start plus
-// the number of cell mates that precede it.  Sums over a run are exact
-// int64 sums of the fixed-point values of the prep pass.
+// the number of cell mates that precede it.  Sums over a run are exact:
+// FP64 sums of the integer fixed-point values of the prep pass, below 2^53.
 
 __host__ __device__ inline int pow2_at_least(int n) {
   int m = 1;
