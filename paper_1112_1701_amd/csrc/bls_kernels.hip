@@ -1394,14 +1394,46 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
 // in FP64 in a fixed lane order combined by a fixed butterfly, so results do
 // not depend on scheduling.
 
+// Wave sums in a fixed order, through DPP moves (registers only, no LDS
+// round trip per step): lanes exchange within quads, then half rows and rows
+// of 16 (every lane then holds its row's sum), then row 0 is added into row
+// 1 and row 2 into row 3 (row_bcast:15), then rows 0-1 into rows 2-3
+// (row_bcast:31); lane 63 holds the total, which is read out to every lane.
+// Lanes a DPP step does not write keep 0, so they add nothing.
+template <int CTRL, int ROWS>
+__device__ inline int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL, ROWS>((int)(unsigned)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL, ROWS>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
-  return v;
+  v = v + dpp_f64<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = v + dpp_f64<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = v + dpp_f64<0x141, 0xf>(v);  // row_half_mirror
+  v = v + dpp_f64<0x140, 0xf>(v);  // row_mirror
+  v = v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 __device__ inline int wave_isum(int v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_i32<0xb1, 0xf>(v);
+  v += dpp_i32<0x4e, 0xf>(v);
+  v += dpp_i32<0x141, 0xf>(v);
+  v += dpp_i32<0x140, 0xf>(v);
+  v += dpp_i32<0x142, 0xa>(v);
+  v += dpp_i32<0x143, 0xc>(v);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // One wave per star: the mean, then the mean squared deviation (two passes,
