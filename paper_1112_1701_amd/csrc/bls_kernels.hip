@@ -1436,20 +1436,54 @@ __device__ inline int wave_isum(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
-// One wave per star: the mean, then the mean squared deviation (two passes,
-// as the definition reads).  A star of up to 512 values is loaded once into
-// registers (8 per lane, all loads in flight together) and both passes run
-// there; longer stars take the second pass from memory again.
-constexpr int kVarRegs = 8;
+// Sums over each half of a wave (lanes 0-31 and 32-63) in a fixed order:
+// the steps of wave_sum up to row_bcast:15, which leave the halves' totals
+// in lanes 31 and 63; every lane receives its own half's total.
+__device__ inline double half_sum(double v) {
+  v = v + dpp_f64<0xb1, 0xf>(v);
+  v = v + dpp_f64<0x4e, 0xf>(v);
+  v = v + dpp_f64<0x141, 0xf>(v);
+  v = v + dpp_f64<0x140, 0xf>(v);
+  v = v + dpp_f64<0x142, 0xa>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo0 = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 31);
+  const int hi0 = __builtin_amdgcn_readlane((int)(b >> 32), 31);
+  const int lo1 = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
+  const int hi1 = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  const bool upper = (threadIdx.x & 32) != 0;
+  const int lo = upper ? lo1 : lo0, hi = upper ? hi1 : hi0;
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ inline int half_isum(int v) {
+  v += dpp_i32<0xb1, 0xf>(v);
+  v += dpp_i32<0x4e, 0xf>(v);
+  v += dpp_i32<0x141, 0xf>(v);
+  v += dpp_i32<0x140, 0xf>(v);
+  v += dpp_i32<0x142, 0xa>(v);
+  const int t0 = __builtin_amdgcn_readlane(v, 31), t1 = __builtin_amdgcn_readlane(v, 63);
+  return (threadIdx.x & 32) ? t1 : t0;
+}
+
+// Half a wave per star (two stars per wave, so half as many waves wait on
+// memory): the mean, then the mean squared deviation (two passes, as the
+// definition reads).  A star of up to 320 values is loaded once into
+// registers (10 per lane, all loads in flight together) and both passes run
+// there; longer stars take the second pass from memory again.  Every lane
+// stays active through the sums: a half past the last star works on an
+// empty one and writes nothing.
+constexpr int kVarLanes = 32;
+constexpr int kVarRegs = 10;
 
 __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (c >= a.ncurves) return;
+  const int lane = threadIdx.x & (kVarLanes - 1);
+  const int c = blockIdx.x * (kBlock / kVarLanes) + (threadIdx.x / kVarLanes);
+  const bool live = c < a.ncurves;
   // The star's offsets and magnitude are loaded together up front (one
   // round trip before the values, none after them).
-  const int64_t off = a.n_off[c], n = a.n_off[c + 1] - off;
-  const double mag = a.mag[c];
+  const int64_t off = live ? a.n_off[c] : 0;
+  const int64_t n = live ? a.n_off[c + 1] - off : 0;
+  const double mag = live ? a.mag[c] : 0.0;
   const double *x = a.x + off;
   const double *w = a.w ? a.w + off : nullptr;
   int cnt = 0, bad = 0;
@@ -1461,10 +1495,10 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
     xv[u] = 0.0;
     kv[u] = false;
   }
-  for (int64_t i0 = lane; i0 < n; i0 += 64 * kVarRegs) {
+  for (int64_t i0 = lane; i0 < n; i0 += kVarLanes * kVarRegs) {
 #pragma unroll
     for (int u = 0; u < kVarRegs; ++u) {
-      const int64_t i = i0 + 64 * u;
+      const int64_t i = i0 + kVarLanes * u;
       xv[u] = i < n ? x[i] : 0.0;
       const double wi = i < n ? (w ? w[i] : 1.0) : 0.0;
       if (!(wi >= 0.0) || isinf(wi)) bad = 1;
@@ -1478,13 +1512,13 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
       ++cnt;
     }
   }
-  s = wave_sum(s);
-  cnt = wave_isum(cnt);
-  bad = wave_isum(bad);
+  s = half_sum(s);
+  cnt = half_isum(cnt);
+  bad = half_isum(bad);
   const double mu = s / (double)cnt;
   double ss = 0.0;
   if (!bad && cnt > 0) {
-    if (n <= 64 * kVarRegs) {
+    if (n <= kVarLanes * kVarRegs) {
 #pragma unroll
       for (int u = 0; u < kVarRegs; ++u) {
         if (!kv[u]) continue;
@@ -1492,7 +1526,7 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
         ss = ss + dv * dv;
       }
     } else {
-      for (int64_t i = lane; i < n; i += 64) {
+      for (int64_t i = lane; i < n; i += kVarLanes) {
         const double wi = w ? w[i] : 1.0;
         if (wi == 0.0) continue;
         const double dv = x[i] - mu;
@@ -1500,8 +1534,8 @@ __global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
       }
     }
   }
-  ss = wave_sum(ss);
-  if (lane != 0) return;
+  ss = half_sum(ss);
+  if (lane != 0 || !live) return;
   if (bad || cnt == 0) {
     a.rms[c] = __longlong_as_double(0x7ff8000000000000ll);
     a.bin[c] = -1;
@@ -2051,7 +2085,7 @@ int launch_window(const WindowArgs &a, int grid, void *stream) {
 int launch_variability(const VarArgs &a, void *stream) {
   if (a.ncurves <= 0 || a.nchips <= 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  const int per = kBlock / 64;
+  const int per = kBlock / kVarLanes;
   hipLaunchKernelGGL(var_rms_kernel, dim3((a.ncurves + per - 1) / per), dim3(kBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
