@@ -505,10 +505,7 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
 
 TileChoice default_tiles(bool weighted) {
   TileChoice tc;
-  // Unit weights: 20 KB of LDS per workgroup leaves room for 8 per CU.  On
-  // the serving sweep it beat 32 KB (p99 at 1000 requests/s 8.5-9.1 ms
-  // against 10.4-10.7, saturation about 4% higher) and 16 KB.
-  tc.lds_budget = weighted ? 40960 : 20480;
+  tc.lds_budget = weighted ? 40960 : 32768;
   tc.tile_cap = kTileMax;
   tc.occupancy = 0;
   return tc;
