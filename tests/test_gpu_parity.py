@@ -412,6 +412,43 @@ def test_detection_crafted_periodograms(bls):
                 assert g["candidate"] == o["candidate"], c
 
 
+def test_detection_beyond_a_million_periods(bls):
+    """Detection of periodograms longer than 2^20 periods (the kernel keeps
+    no per-period state in LDS, so their length is limited only by the
+    batch): two curves of 2^21 + 3 periods, random SR with a few strong
+    peaks and their harmonics, 16 peaks; indices bit-exact against the
+    oracle."""
+    import torch
+    rng = np.random.default_rng(85)
+    m = (1 << 21) + 3
+    per = np.geomspace(0.1, 30.0, m)
+    srs = []
+    for c in range(2):
+        sr = rng.gamma(2.0, 0.5, m).astype(np.float32)
+        for P in (0.7 + c, 2.3, 5.1):
+            for h in (1.0, 0.5, 2.0, 1.0 / 3.0, 3.0):
+                j = int(np.argmin(np.abs(per - h * P)))
+                sr[max(j - 50, 0):j + 50] += np.float32(20.0 / h)
+        srs.append(sr)
+    _say("detection long periodograms", m)
+    dev = torch.device("cuda:0")
+    per_d = torch.tensor(per, device=dev)
+    sr_d = torch.tensor(np.concatenate(srs), device=dev)
+    with bls.Plan(max_curves=2, max_points=1 << 12, max_periods=2 * m) as p:
+        det = bls.bls_detect_device(p.handle, np.array([0, 4, 8]), per_d, None,
+                                    200, 0.01, 0.1, sr_d, max_peaks=16,
+                                    window=0.002, sde_threshold=5.0)
+    for c in range(2):
+        o = oracle.detect(srs[c].astype(np.float64), per, max_peaks=16,
+                          window=0.002, threshold=5.0)
+        g = det[c]
+        assert np.array_equal(g["peak_index"], o["peak_index"]), c
+        for k in ("mean", "std", "sde"):
+            gv = g[k if k == "sde" else k + "_sr"]
+            assert abs(gv - o[k]) <= 1e-12 * max(abs(o[k]), 1e-30), (c, k)
+        assert g["candidate"] == o["candidate"]
+
+
 def test_single_bin_boxes(bls, plan):
     """kmax = 1 (20 bins, q up to 0.05): each period's histogram is its bins
     plus one clamp word, so the LDS tile must hold nbins + 1 words per
