@@ -505,7 +505,11 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
 
 TileChoice default_tiles(bool weighted) {
   TileChoice tc;
-  tc.lds_budget = weighted ? 40960 : 32768;
+  // The same 32 KB for both paths: one-curve calls on uneven weighted curves
+  // ran at 1.97e11 trial-period points/s with it, against 1.92e11 with 40 KB
+  // and 1.94e11 with 24 KB.
+  (void)weighted;
+  tc.lds_budget = 32768;
   tc.tile_cap = kTileMax;
   tc.occupancy = 0;
   return tc;
