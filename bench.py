@@ -1,13 +1,23 @@
 """Benchmark: BLS trial-periods x points per second on one MI355X.
 
-Default run (the headline line): one step = the whole search of the uniform
-batch workload (4096 light curves x N = 2000 epochs, 20000 shared
-log-spaced trial periods 0.2-10 d, 300 phase bins, box duty cycles
-0.01-0.10) with the inputs already in HBM: prep (centring, t0, fixed-point
-encoding), fold + bin, box scan, per-period argmax and per-curve best period,
-all in the HIP library, replayed as one HIP graph.  Prints ONE JSON line with
-the metric, the roofline of the dominant kernel (the search kernel) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+Default run (the headline line): one step = the whole search of the
+high-cadence long-baseline workload (256 light curves x N = 50000 epochs on a
+1-minute grid over 120 nights, 100000 shared log-spaced trial periods
+0.1-20 d, 1000 phase bins, box duty cycles 0.005-0.05), the largest
+single-GPU workload in trial-period x points, with the inputs already in HBM:
+prep (centring, t0, fixed-point encoding), fold + bin, box scan, per-period
+argmax and per-curve best period, all in the HIP library, replayed as HIP
+graphs.  The search kernel's duration is read from the HIP events the library
+records around it on its stream in every timed step.  Prints ONE JSON line
+with the metric, the roofline of the dominant kernel (the search kernel,
+per-unit operation counts against the published FP64/FP32 peaks), its LDS
+traffic against the LDS peak, the FP64 CPU oracle timed on a bounded sample
+of the same workload, and as extra keys: the uniform and uneven batch
+workloads' throughput, the served form's p50/p99 latency at two arrival
+rates, and the end-to-end time of the host-array call (PCIe included).
+
+--workload picks another batch workload for the headline (uniform, uneven,
+plain); --no-extras drops the extra keys (profiling runs).
 
 --suite: one JSON line per workload (plain, uniform, uneven, long baseline):
 batched throughput, the plain per-curve GPU form for comparison, and the
@@ -32,40 +42,66 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue of gfx950, counted in FP32 issue slots: FP32 vector
-# instructions issue at 128 lanes per CU per clock (256 CUs x 128 x 2.4 GHz
-# = 78.6 T lane-ops/s, the published 157.3 TFLOP/s FP32 vector peak with an
-# FMA as two), FP64 and 32-bit integer ones at half that (78.6 TFLOP/s FP64),
-# so each of those takes two slots.  The ALU rooflines quote two FLOP per
-# slot, which makes their peak the published 157.3 TFLOP/s.
-FP32_SLOTS_PER_S = 256 * 128 * 2.4e9
-ALU_PEAK_TFLOPS = 2 * FP32_SLOTS_PER_S / 1e12
-# Algorithmic slots: per trial-period x point the fold, four FP64 operations
-# (multiply, fractional part, multiply, truncate) and one integer (the bin
-# address), 2 slots each; per box evaluation six FP32 operations (the two
-# running sums, theta R, S^2, S^2 - theta R (W - R) and the comparison).
+# Published MI355X peaks (dense, no sparsity).
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+# LDS: 128 bytes per clock per CU (32 banks of 4 bytes), 256 CUs, 2.4 GHz.
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
+# Algorithmic work of the binned search, per unit:
+#   per trial-period x point, the fold in FP64: multiply d f, floor,
+#   subtract (the phase), multiply by nbins, truncate: 5 operations;
+#   per box evaluation, FP32: the two window sums, theta R, S^2,
+#   S^2 - theta R (W - R), the comparison and its selects: 10 operations.
+# The low ends of the ranges in the design notes, so the fraction is not
+# inflated.  FP64 operations count against the FP64 peak, FP32 ones against
+# the FP32 peak; the roofline quotes FP32-equivalent TFLOP/s (an FP64
+# operation counts as two, the ratio of the peaks).
+FP64_OPS_PER_TRIAL_POINT = 5
+FP32_OPS_PER_BOX_EVAL = 10
+# LDS bytes per unit: one 8-byte atomic per trial-period x point (two for
+# weighted curves), one 8-byte read per box evaluation.
+LDS_BYTES_PER_TRIAL_POINT = 8
+LDS_BYTES_PER_BOX_EVAL = 8
+# The former issue-slot count (FP32 issue slots: 10 per trial-period x point,
+# 6 per box evaluation, two FLOP per slot), kept as a separate figure.
 SLOTS_PER_TRIAL_POINT = 10
 SLOTS_PER_BOX_EVAL = 6
+FP32_SLOTS_PER_S = 256 * 128 * 2.4e9
+ALU_PEAK_TFLOPS = 2 * FP32_SLOTS_PER_S / 1e12
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(batch, budget_s: float):
-    """FP64 oracle on the first curves of the batch until budget_s elapses."""
+    """FP64 oracle on whole curves of the batch, in order, until budget_s."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or \
         os.cpu_count()
     oracle.build(force=False)
-    done_pp = 0.0
+    done_pp = done_ev = 0.0
     t0 = time.perf_counter()
     ncur = 0
     for c in range(batch.ncurves):
         lc = batch.curve(c)
-        oracle.search(lc.t, lc.x, lc.w, lc.periods, lc.nbins, lc.qmin,
-                      lc.qmax, nthreads=threads)
+        o = oracle.search(lc.t, lc.x, lc.w, lc.periods, lc.nbins, lc.qmin,
+                          lc.qmax, nthreads=threads)
         done_pp += float(lc.n) * lc.periods.size
+        done_ev += float(lc.nbins) * (o.kmax - o.kmin + 1) * lc.periods.size
         ncur += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -73,7 +109,8 @@ def cpu_baseline(batch, budget_s: float):
     return {"value": done_pp / el, "unit": "trial-periods*points/s",
             "cores": threads, "kind": "oracle",
             "sample": "first %d of %d curves, all their periods, %.1f s"
-                      % (ncur, batch.ncurves, el)}
+                      % (ncur, batch.ncurves, el),
+            "box_evals_per_s": done_ev / el, "cpu_model": cpu_model()}
 
 
 class DeviceBatch:
@@ -104,31 +141,33 @@ class DeviceBatch:
 
 
 def time_batched(bls, db, steps, warmup):
-    """Graph-replayed steps; returns (ms/step, stats, per-step device ms)."""
+    """Graph-replayed steps, bracketed by device synchronizations.
+
+    Returns (ms per step, call statistics, search-kernel ms of each timed
+    step from the events the library records around the kernel on its
+    stream; the last 64 steps when there are more).
+    """
     import torch
     plan = bls.Plan(**db.cap)
-    stream = torch.cuda.ExternalStream(bls.bls_get_stream(plan.handle))
     for _ in range(max(warmup, 1)):
         db.call(bls, plan.handle)
         bls.bls_synchronize(plan.handle)
     st = bls.bls_last_stats(plan.handle)
+    bls.bls_kernel_times_reset(plan.handle)
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    evs[0].record(stream)
     for k in range(steps):
         db.call(bls, plan.handle)
-        evs[k + 1].record(stream)
     bls.bls_synchronize(plan.handle)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    kms = bls.bls_kernel_times(plan.handle, min(steps, 64))
     plan.close()
-    dev_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
-    return (t1 - t0) * 1e3 / steps, st, dev_ms
+    return (t1 - t0) * 1e3 / steps, st, kms
 
 
 def time_kernel(bls, db, reps):
-    """The search kernel alone (non-graph launch bracketed by HIP events)."""
+    """The search kernel of non-graph calls (HIP events around the launch)."""
     kplan = bls.Plan(flags=bls.BLS_NO_GRAPH, **db.cap)
     kms = []
     for _ in range(max(reps, 3)):
@@ -171,58 +210,165 @@ def time_plain(bls, db, max_curves, budget_s=5.0):
     return {"value": done_pp / el, "curves": ncur, "seconds": el}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_kernel_uniform4096_traffic.txt")
+def time_host_arrays(bls, b, reps=2):
+    """End to end from host arrays (bls_search_batch): uploads, the search,
+    downloads and the widening to FP64 outputs; the last of reps calls."""
+    with bls.Plan(max_curves=b.ncurves, max_points=b.total_points(),
+                  max_periods=int(b.p_off[-1]) if b.p_off is not None
+                  else b.ncurves * b.periods.size,
+                  max_nbins=int(max(b.nbins))) as p:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            bls.bls_search_batch(p.handle, b.n_off, b.t, b.x, b.w, b.periods,
+                                 b.p_off, b.nbins, b.qmin, b.qmax)
+            el = time.perf_counter() - t0
+        st = bls.bls_last_stats(p.handle)
+    return {"ms": el * 1e3, "device_ms": st["total_ms"],
+            "search_kernel_ms": st["search_ms"],
+            "trial_points_per_s": b.trial_points() / el}
+
+
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1112_1701_amd", "csrc", "bls_kernels.hip")
+PROFILE_TAG = {"long": "long256", "uniform": "uniform4096",
+               "uneven": "uneven10000", "plain": "plain1"}
 
 
-def measured_traffic():
-    """HBM bytes per search-kernel launch from the committed counter runs.
-
-    The file records the counters' bytes per launch and the SHA-256 of the
-    kernel source they were taken on; once the source differs the figure no
-    longer describes this kernel and None is returned.
-    """
+def _profile_record(kind, workload):
+    """key: value lines of profiles/search_kernel_<workload>_<kind>.txt, or
+    None when missing or taken on another version of the kernel source (the
+    file records the SHA-256 of the source its counters were taken on)."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", "search_kernel_%s_%s.txt"
+                        % (PROFILE_TAG.get(workload, workload), kind))
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line:
+        if ":" in line and not line.startswith((" ", "#")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha256") != src:
         return None
+    return vals
+
+
+def measured_traffic(workload):
+    """HBM bytes per search-kernel launch from the committed counter runs."""
+    vals = _profile_record("traffic", workload)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
 
 
 def roofline(pp, evals, k_ms, traffic=None):
-    r = _alu_roofline(SLOTS_PER_TRIAL_POINT * pp + SLOTS_PER_BOX_EVAL * evals,
-                      k_ms)
-    r["traffic"] = traffic
-    return r
+    """The search kernel against the published FP64 and FP32 peaks: the
+    algorithmic operations (FP64_OPS_PER_TRIAL_POINT, FP32_OPS_PER_BOX_EVAL)
+    over the launch's duration, in FP32-equivalent TFLOP/s."""
+    t = k_ms * 1e-3
+    flop32 = 2 * FP64_OPS_PER_TRIAL_POINT * pp + FP32_OPS_PER_BOX_EVAL * evals
+    achieved = flop32 / t / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": traffic}
+
+
+def issue_slot_fraction(pp, evals, k_ms):
+    """The former figure: FP32 issue slots of the kernel's own instruction
+    mix over the issue peak."""
+    slots = SLOTS_PER_TRIAL_POINT * pp + SLOTS_PER_BOX_EVAL * evals
+    return 2 * slots / (k_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS
+
+
+def lds_roofline(pp, evals, k_ms, weighted, workload):
+    """Algorithmic LDS bytes of the search kernel over the LDS peak, with
+    the bank-conflict rate and LDS activity of the committed counter run."""
+    nb = (2 if weighted else 1) * LDS_BYTES_PER_TRIAL_POINT * pp + \
+        LDS_BYTES_PER_BOX_EVAL * evals
+    achieved = nb / (k_ms * 1e-3) / 1e12
+    out = {"achieved": achieved, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+           "frac": achieved / LDS_PEAK_TBS, "bytes": nb,
+           "bank_conflict_frac": None, "lds_active_frac": None}
+    vals = _profile_record("lds", workload)
+    if vals:
+        for k in ("bank_conflict_frac", "lds_active_frac"):
+            try:
+                out[k] = float(vals[k])
+            except (KeyError, ValueError):
+                pass
+    return out
+
+
+WORKLOADS = {
+    "long": ("high-cadence long baseline: 256 light curves x N=50000 on a "
+             "1-minute grid over 120 nights, 100000 log periods 0.1-20 d, "
+             "nbins=1000, q 0.005-0.05, unit weights"),
+    "uniform": ("uniform batch: 4096 light curves x N=2000, 20000 log periods "
+                "0.2-10 d, nbins=300, q 0.01-0.10, unit weights"),
+    "uneven": ("uneven batch: 10000 light curves, N log-uniform 200-10000, "
+               "5000-40000 own log periods 0.2-10 d, nbins 200-500, "
+               "q 0.01-0.10, weights 1/sigma^2"),
+    "plain": ("plain: 1 light curve x N=1000, 5000 log periods 0.2-10 d, "
+              "nbins=200, q 0.01-0.10"),
+}
+
+
+def _generate(name):
+    import synth
+    return {"plain": lambda: _as_batch(synth.config1()),
+            "uniform": synth.config2, "uneven": synth.config3,
+            "long": synth.config4}[name]()
+
+
+def extra_batch(bls, name, steps):
+    """Graph-replayed throughput of another batch workload."""
+    b = _generate(name)
+    db = DeviceBatch(b)
+    ms_step, st, kms = time_batched(bls, db, steps, 1)
+    pp, evals = st["trial_points"], st["box_evals"]
+    k_ms = sum(kms) / len(kms)
+    out = {"workload": WORKLOADS[name], "ms_per_step": ms_step,
+           "trial_points_per_s": pp / (ms_step * 1e-3),
+           "box_evals_per_s": evals / (ms_step * 1e-3),
+           "search_kernel_ms": k_ms,
+           "roofline_frac": roofline(pp, evals, k_ms)["frac"]}
+    del db
+    return out
 
 
 def headline(args):
-    import numpy as np
-
     import paper_1112_1701_amd as bls
-    import synth
     import torch
     torch.cuda.set_device(0)
-    log("generating workload")
-    b = synth.config2(args.curves)
+    log("generating workload", args.workload)
+    b = _generate(args.workload)
+    weighted = b.w is not None
     db = DeviceBatch(b)
     log("timed", args.steps)
-    ms_step, st, dev_ms = time_batched(bls, db, args.steps, args.warmup)
+    ms_step, st, kms = time_batched(bls, db, args.steps, args.warmup)
     pp, evals = st["trial_points"], st["box_evals"]
-    log("kernel timing")
-    k_ms, kst = time_kernel(bls, db, args.steps)
+    k_ms = sum(kms) / len(kms)
+    extras = {}
+    if not args.no_extras:
+        log("end to end from host arrays")
+        extras["end_to_end_host_arrays"] = time_host_arrays(bls, b)
+        del db
+        for name in ("uniform", "uneven"):
+            if name != args.workload:
+                log("extra", name)
+                extras[name] = extra_batch(bls, name, 3)
+        log("serving")
+        recs = suite_serving(bls, [500.0, 1000.0], 300, 3000, 3.0)
+        extras["served"] = {
+            "workload": "Poisson arrivals; requests N log-U[500, 20000], "
+                        "5000-100000 log periods 0.2-10 d, nbins 200-1000",
+            "rates": [{k: r[k] for k in ("rate_req_per_s", "p50_ms",
+                                         "p99_ms", "trial_points_per_s",
+                                         "completed_per_s")}
+                      for r in recs]}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -240,29 +386,32 @@ def headline(args):
         "vs_baseline": None,
         "dtype": "f64 phase, exact int64 bins, f32 scan",
         "data": "synthetic",
-        "config": {"workload": "uniform batch: %d light curves x N=2000, "
-                               "20000 log periods 0.2-10 d, nbins=300, "
-                               "q 0.01-0.10, unit weights" % b.ncurves,
+        "config": {"workload": WORKLOADS[args.workload],
                    "curves": b.ncurves, "points": int(b.total_points()),
-                   "periods": int(b.periods.size), "nbins": 300,
+                   "trial_points": pp, "box_evals": evals,
                    "parallelism": "1 GPU"},
         "box_evals_per_s": evals / (ms_step * 1e-3),
-        "device_ms_per_step": float(np.median(dev_ms)),
         "search_kernel_ms": k_ms,
-        "launch": {"grid": kst["grid"], "block": kst["block"],
-                   "lds_bytes": kst["lds_bytes"],
-                   "work_items": kst["work_items"]},
-        "roofline": roofline(pp, evals, k_ms, measured_traffic()),
+        "search_kernel_ms_per_step": kms,
+        "launch": {"grid": st["grid"], "block": st["block"],
+                   "lds_bytes": st["lds_bytes"],
+                   "work_items": st["work_items"]},
+        "roofline": roofline(pp, evals, k_ms, measured_traffic(args.workload)),
+        "issue_slot_frac": issue_slot_fraction(pp, evals, k_ms),
+        "lds_roofline": lds_roofline(pp, evals, k_ms, weighted,
+                                     args.workload),
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 
 def suite_batch(name, b, args, bls):
     log("suite", name)
     db = DeviceBatch(b)
-    ms_step, st, _ = time_batched(bls, db, args.suite_steps, 1)
-    k_ms, kst = time_kernel(bls, db, 2)
+    ms_step, st, kms = time_batched(bls, db, args.suite_steps, 1)
+    k_ms = sum(kms) / len(kms)
+    _, kst = time_kernel(bls, db, 2)
     plain = time_plain(bls, db, 64)
     pp, evals = st["trial_points"], st["box_evals"]
     cpu = None
@@ -279,6 +428,9 @@ def suite_batch(name, b, args, bls):
            "launch": {"grid": kst["grid"], "lds_bytes": kst["lds_bytes"],
                       "work_items": kst["work_items"]},
            "roofline": roofline(pp, evals, k_ms),
+           "issue_slot_frac": issue_slot_fraction(pp, evals, k_ms),
+           "lds_roofline": lds_roofline(pp, evals, k_ms, b.w is not None,
+                                        name),
            "cpu_baseline": cpu}
     del db
     return rec
@@ -349,7 +501,6 @@ def suite_serving(bls, rates, pool_size, max_requests, seconds):
 # run step.
 SLOTS_WINDOW_PP, SLOTS_WINDOW_EPOCH = 10, 8
 SLOTS_UNBINNED_PP, SLOTS_UNBINNED_STEP = 20, 16
-HBM_PEAK_GBS = 8000.0
 
 
 def _alu_roofline(slots, k_ms):
@@ -585,9 +736,6 @@ def suite(args):
     import torch
     torch.cuda.set_device(0)
     names = args.workloads.split(",")
-    gens = {"plain": lambda: _as_batch(synth.config1()),
-            "uniform": synth.config2, "uneven": synth.config3,
-            "long": synth.config4}
     extra = {"window": suite_window, "variability": suite_variability,
              "unbinned": suite_unbinned, "detect": suite_detect}
     for name in names:
@@ -602,7 +750,7 @@ def suite(args):
             print(json.dumps({"workload": "serving", "sweep": recs}),
                   flush=True)
             continue
-        rec = suite_batch(name, gens[name](), args, bls)
+        rec = suite_batch(name, _generate(name), args, bls)
         print(json.dumps(rec), flush=True)
 
 
@@ -633,7 +781,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--curves", type=int, default=4096)
+    ap.add_argument("--workload", default="long",
+                    choices=sorted(WORKLOADS))
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--suite", action="store_true")

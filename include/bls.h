@@ -175,7 +175,12 @@ typedef struct {
  * on the device.  Asynchronous on the plan's stream: the device arrays are
  * borrowed until bls_synchronize returns.  Curves whose data is invalid get
  * SR = NaN and are reported by bls_synchronize.  Repeated calls with the
- * same batch description replay a captured HIP graph.
+ * same batch description replay captured HIP graphs.  Several calls may be
+ * queued on one plan without synchronizing in between, with the same or
+ * different batches: a call that must rewrite the plan's staged batch
+ * description first waits (on the host) until the copies of the queued
+ * calls have read it.  They share the plan's prepared-point scratch, so
+ * they run one after the other in stream order.
  */
 int bls_search_device(bls_plan *plan, const bls_batch *batch,
                       const bls_device_results *out);
@@ -268,7 +273,7 @@ int bls_detect_device(bls_plan *plan, const bls_batch *batch, const float *sr,
  * least min_eclipses eclipses of a binary with a given period fall on
  * observations, given the real cadence with its daytime and weather gaps
  * (the simulation behind the paper's detection-efficiency figure, section
- * 3).  Per cadence and trial period P (f = 1/P):
+ * 5, Discussion and conclusions).  Per cadence and trial period P (f = 1/P):
  *   the kept times (weight > 0; all if weights is NULL) are folded into
  *   nphase phase bins as in the search (t0 = min kept time, bin =
  *   min(trunc(frac((t - t0) f) nphase), nphase - 1), FP64);
@@ -375,6 +380,16 @@ typedef struct {
 } bls_call_stats;
 
 int bls_last_stats(const bls_plan *plan, bls_call_stats *out);
+
+/* Device durations of the search kernel (or unbinned kernel) launches of
+ * the plan's search calls since the last bls_kernel_times_reset, measured by
+ * HIP events recorded on the plan's stream right before and after each
+ * launch (graph replays included: the kernel is its own graph).  Waits for
+ * the plan's stream, then writes the most recent min(max, available)
+ * durations in ms, oldest first, to ms[] and their number to *count; the
+ * plan keeps the last 64.  Errors: INVALID_ARG, DEVICE. */
+int bls_kernel_times(bls_plan *plan, float *ms, int32_t max, int32_t *count);
+int bls_kernel_times_reset(bls_plan *plan);
 
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching.  Requests (one light curve with

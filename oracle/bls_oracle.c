@@ -435,9 +435,10 @@ int bls_oracle_detect(const double *sr, const double *periods, int64_t m,
 
 /*
  * Eclipse detection efficiency of an observing cadence (the simulation
- * behind the paper's detection-efficiency figure, section 3: the chance that
- * at least two eclipses of a binary of given period fall on observations,
- * given the real cadence with its daytime and weather gaps).  Readings:
+ * behind the paper's detection-efficiency figure, section 5, Discussion and
+ * conclusions: the chance that at least two eclipses of a binary of given
+ * period fall on observations, given the real cadence with its daytime and
+ * weather gaps).  Readings:
  *   W1  only the times matter; points with weight 0 are not observations
  *       (a NULL weight array keeps every point); t0 = min kept time;
  *   W2  eclipse epochs are a grid of nphase phase offsets j / nphase; the

@@ -22,6 +22,8 @@ from .api import (  # noqa: F401
     bls_last_error,
     bls_status_string,
     bls_last_stats,
+    bls_kernel_times,
+    bls_kernel_times_reset,
     bls_debug_phase_bins,
     bls_detect_device,
     bls_eclipse_window_device,

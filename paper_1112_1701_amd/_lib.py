@@ -170,6 +170,8 @@ def load():
         "bls_last_error": (C.c_int, [P, P, C.c_size_t]),
         "bls_status_string": (C.c_char_p, [C.c_int]),
         "bls_last_stats": (C.c_int, [P, P]),
+        "bls_kernel_times": (C.c_int, [P, P, I32, P]),
+        "bls_kernel_times_reset": (C.c_int, [P]),
         "bls_debug_phase_bins": (C.c_int, [P, P, I64, D, I32, P]),
         "bls_detect_device": (C.c_int, [P, P, P, I32, D, D, P]),
         "bls_eclipse_window_device": (C.c_int, [P, P, I32, D, I32, P]),

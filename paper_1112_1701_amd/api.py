@@ -93,6 +93,20 @@ def bls_last_stats(plan) -> dict:
     return {f: getattr(s, f) for f, _ in L.BlsCallStats._fields_}
 
 
+def bls_kernel_times(plan, max_count: int = 64) -> list:
+    """Search-kernel durations (ms) of the plan's calls since the last reset,
+    oldest first (HIP events around each launch on the plan's stream)."""
+    buf = (C.c_float * max(int(max_count), 1))()
+    n = C.c_int32(0)
+    _check(L.load().bls_kernel_times(plan, buf, int(max_count), C.byref(n)),
+           plan)
+    return [float(buf[i]) for i in range(n.value)]
+
+
+def bls_kernel_times_reset(plan) -> None:
+    _check(L.load().bls_kernel_times_reset(plan), plan)
+
+
 def bls_debug_phase_bins(plan, times, period: float, nbins: int):
     """Phase bin the device assigns to each point at one period (diagnostic)."""
     t = _f64(times)

@@ -113,7 +113,8 @@ double time_candidate(bls_plan *p, std::vector<CurveShape> &shapes, bool weighte
       hipMemcpyAsync(p->d_seg_curve, p->h_seg_curve, sizeof(int32_t) * pb.nseg,
                      hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(p->d_seg_tile0, p->h_seg_tile0, sizeof(int32_t) * pb.nseg,
-                     hipMemcpyHostToDevice, st) != hipSuccess)
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      desc_mark(p) != BLS_OK)
     return -1.0;
   SearchArgs a;
   a.curves = p->d_curves;

@@ -56,6 +56,11 @@ struct CurveDesc {
   // ---- unbinned search only (host)
   double qlo;           // duty-cycle limits of a box, in phase
   double qhi;
+  // ---- written by the prep kernel: exact totals in scan units (sums of the
+  // fixed-point values times 2^-qbits), for boxes evaluated through their
+  // complement and for the reported statistic
+  double Wtot;          // total weight (the kept count for unit weights)
+  double Stot;          // total signal (about 0: the values are centred)
 };
 
 struct PrepArgs {

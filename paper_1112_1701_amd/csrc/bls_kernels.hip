@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
   const int es = scale_exponent(my, qbits);
   const int ew = weighted ? scale_exponent(mw, qbits) : qbits;
 
-  // Pass 3: encode.
-  long long sqw = 0, unused = 0;
+  // Pass 3: encode; exact totals of the encoded weights and values.
+  long long sqw = 0, sq = 0;
   for (int64_t i = tid; i < n; i += kBlock) {
     const double wi = weighted ? a.w[off + i] : 1.0;
     if (wi == 0.0) {
@@ -249,14 +249,16 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
     const double yi = a.x[off + i] - xbar;
     const double v = weighted ? wi * yi : yi;
     a.dt[off + i] = a.t[off + i] - tmin;
-    a.q[off + i] = __double2int_rn(ldexp(v, es));
+    const int qi = __double2int_rn(ldexp(v, es));
+    a.q[off + i] = qi;
+    sq += qi;
     if (weighted) {
       const int qwi = __double2int_rn(ldexp(wi, ew));
       a.qw[off + i] = qwi;
       sqw += qwi;
     }
   }
-  block_isum2(sqw, unused, ia, ib);
+  block_isum2(sqw, sq, ia, ib);
 
   if (tid == 0) {
     cd->t0 = tmin;
@@ -266,6 +268,9 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(PrepArgs a) {
     cd->ew = ew;
     cd->out_scale = ldexp(1.0, ew - es);
     cd->Wf = weighted ? (float)ldexp((double)sqw, -qbits) : (float)cnt;
+    // |sums| < 2^53, so both totals are exact in FP64
+    cd->Wtot = weighted ? ldexp((double)sqw, -qbits) : (double)cnt;
+    cd->Stot = ldexp((double)sq, -qbits);
     cd->n_eff = (int32_t)cnt;
     cd->status = kCurveOk;
   }
@@ -527,20 +532,21 @@ __device__ __forceinline__ void consider_w(float R, float S, float d, int m, con
   }
 }
 
-// One lane task, weighted curves: as for unit weights, d = W - R is kept by
-// subtraction and u = theta R by fused multiply-add, so the screen
-// S^2 >= u d costs six operations per box (ha: the period's (R, S) bins
-// from start j; hc: their counts in .x, read only for boxes that pass).
+// One lane task, weighted curves.  R is a running sum of the box's weight
+// (positive terms, so its relative error stays within k roundings) and
+// d = W - R is formed per box; u = theta R by fused multiply-add, so the
+// screen S^2 >= u d costs seven operations per box (ha: the period's (R, S)
+// bins from start j; hc: their counts in .x, read only for boxes that pass).
 template <bool DIP>
 __device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float2 *hc, int kmin,
                                                    int kmax, float Wf, float thr, float nmax1,
                                                    float mipf, bool need_counts, float &bn,
                                                    float &bd, int &bm) {
-  float d = Wf, S = 0.0f, u = 0.0f;
+  float R = 0.0f, S = 0.0f, u = 0.0f;
   int m = 0;
   for (; m < kmin - 1; ++m) {
     const float2 e = ha[m];
-    d -= e.x;
+    R += e.x;
     S += e.y;
     u = fmaf(thr, e.x, u);
   }
@@ -549,40 +555,86 @@ __device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float
   bm = -1;
   for (; m + 4 <= kmax; m += 4) {
     const float2 e0 = ha[m], e1 = ha[m + 1], e2 = ha[m + 2], e3 = ha[m + 3];
-    const float d0 = d - e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
-    const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
-    const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
-    const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
+    const float R0 = R + e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
+    const float R1 = R0 + e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
+    const float R2 = R1 + e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
+    const float R3 = R2 + e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
     // as for unit weights: the largest x = S^2 - u d of the four decides,
     // and the rare boxes that pass are recomputed from the group's start
-    const float x0 = fmaf(-u0, d0, S0 * S0);
-    const float x1 = fmaf(-u1, d1, S1 * S1);
-    const float x2 = fmaf(-u2, d2, S2 * S2);
-    const float x3 = fmaf(-u3, d3, S3 * S3);
+    const float x0 = fmaf(-u0, Wf - R0, S0 * S0);
+    const float x1 = fmaf(-u1, Wf - R1, S1 * S1);
+    const float x2 = fmaf(-u2, Wf - R2, S2 * S2);
+    const float x3 = fmaf(-u3, Wf - R3, S3 * S3);
     if (fmaxf(fmaxf(x0, x1), fmaxf(x2, x3)) >= 0.0f) {
-      float dd = d, SS = S, uu = u;
+      float RR = R, SS = S, uu = u;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float2 e = ha[m + i];
-        dd -= e.x;
+        RR += e.x;
         SS += e.y;
         uu = fmaf(thr, e.x, uu);
+        const float dd = Wf - RR;
         if (fmaf(-uu, dd, SS * SS) >= 0.0f)
-          consider_w<DIP>(Wf - dd, SS, dd, m + i, hc, need_counts, nmax1, mipf, bn, bd, bm);
+          consider_w<DIP>(RR, SS, dd, m + i, hc, need_counts, nmax1, mipf, bn, bd, bm);
       }
     }
-    d = d3;
+    R = R3;
     S = S3;
     u = u3;
   }
   for (; m < kmax; ++m) {
     const float2 e = ha[m];
-    d -= e.x;
+    R += e.x;
     S += e.y;
     u = fmaf(thr, e.x, u);
-    if (S * S >= u * d)
-      consider_w<DIP>(Wf - d, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
+    const float d = Wf - R;
+    if (S * S >= u * d) consider_w<DIP>(R, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
   }
+}
+
+// Boxes wider than half the bins, evaluated through their complement: the
+// k' = nb - k bins that follow the box.  A wide box's own sums cancel (the
+// values are centred), so its signal is taken as Stot - S' from the exact
+// total and the complement's short running sum, its weight as W - R', and
+// the weight outside it is R'.  One lane task is complement start j1 with
+// widths k' = k1lo .. k1hi, i.e. boxes (j1 + k' mod nb, nb - k').  Exact
+// ties go to the smaller k, i.e. the larger k', hence >= along the task.
+// Returns the task's best key (0 if none).  h: (R, S) bins from j1; hc:
+// their counts in .x (weighted curves; unit weights count in .x of h).
+template <bool WEIGHTED, bool DIP>
+__device__ inline unsigned long long scan_task_complement(const float2 *h, const float2 *hc,
+                                                          int j1, int k1lo, int k1hi, int nb,
+                                                          float Wf, float Stot, float neff,
+                                                          float mipf) {
+  float R1 = 0.0f, S1 = 0.0f, C1 = 0.0f;
+  float bn = 0.0f, bd = 1.0f;
+  int bk = -1;
+  for (int m = 0; m < k1hi; ++m) {
+    const float2 e = h[m];
+    R1 += e.x;
+    S1 += e.y;
+    if (WEIGHTED) C1 += hc[m].x;
+    if (m + 1 < k1lo) continue;
+    const float Sin = Stot - S1;
+    const float num = Sin * Sin;
+    const float den = (Wf - R1) * R1;
+    // points in the box: neff - (points outside), at least mip, at most neff - 1
+    const float cout = WEIGHTED ? C1 : R1;
+    bool ok = (num > 0.0f) & (den > 0.0f) & (num * bd >= bn * den) & (cout >= 1.0f) &
+              (neff - cout >= mipf);
+    if (DIP) ok = ok & (Sin < 0.0f);
+    if (ok) {
+      bn = num;
+      bd = den;
+      bk = m + 1;
+    }
+  }
+  if (bk < 0) return 0ull;
+  const int k = nb - bk;
+  const int j = j1 + bk >= nb ? j1 + bk - nb : j1 + bk;
+  const float v = bn * __builtin_amdgcn_rcpf(bd);
+  const unsigned idx = __umul24((unsigned)k, (unsigned)nb) + (unsigned)j;
+  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
 // Key of a lane's best box: its value (any consistent rounding; exact ties
@@ -612,16 +664,16 @@ __device__ inline void seed_best_weighted(const unsigned long long *s_hist,
     const int j = (int)(__umul24((unsigned)(q % kSeeds), (unsigned)nb) / kSeeds);
     const float2 *h =
         reinterpret_cast<const float2 *>(s_hist) + __umul24((unsigned)t, (unsigned)(2 * HS)) + j;
-    float d = Wf, S = 0.0f;
+    float R = 0.0f, S = 0.0f;
     for (int i = 0; i < kmin; ++i) {
       const float2 e = h[i];
-      d -= e.x;
+      R += e.x;
       S += e.y;
     }
     float bn = 0.0f, bd = 1.0f;
     int bm = -1;
     const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
-    consider_w<DIP>(Wf - d, S, d, kmin - 1, h + HS, need_counts, nmax1, mipf, bn, bd, bm);
+    consider_w<DIP>(R, S, Wf - R, kmin - 1, h + HS, need_counts, nmax1, mipf, bn, bd, bm);
     if (bm >= 0)
       __hip_atomic_fetch_max(&s_best[t], box_key(bn, bd, bm, j, nb), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -744,8 +796,11 @@ void search_kernel(SearchArgs a) {
     const int nb = cd.nbins;
     const int kmin = cd.kmin;
     const int kmax = cd.kmax;
-    const int HB = nb + max(kmax - 1, 1);  // bins, then clamp word / wrap copy
-    const int HS = max(cd.hstride, HB);    // words between periods' planes
+    // Widths up to half the bins are scanned directly, wider ones through
+    // their complement; neither reads more than kscan - 1 bins past the end.
+    const int kscan = min(kmax, nb >> 1);
+    const int HB = nb + max(kscan - 1, 1);  // bins, then clamp word / wrap copy
+    const int HS = max(cd.hstride, HB);     // words between periods' planes
 
     // Clear the tile's histograms; frequencies f = 1/P (IEEE division).
     for (int i = tid; i < np * HS * wpb; i += kBlock) s_hist[i] = 0ull;
@@ -804,9 +859,9 @@ void search_kernel(SearchArgs a) {
       }
     }
     __syncthreads();
-    // Wrap-around: bins 0 .. kmax-2 repeated after bin nb-1.
-    if (kmax > 1) {
-      const int ext = kmax - 1;
+    // Wrap-around: bins 0 .. kscan-2 repeated after bin nb-1.
+    if (kscan > 1) {
+      const int ext = kscan - 1;
       for (int i = tid; i < np * ext; i += kBlock) {
         const int t = i / ext;
         const int e = i - t * ext;
@@ -816,7 +871,7 @@ void search_kernel(SearchArgs a) {
       }
     }
     __syncthreads();
-    if (WEIGHTED) {
+    if (WEIGHTED && kmin <= kscan) {
       seed_best_weighted<DIP>(s_hist, s_best, s_nonempty, np, nb, HS, kmin, kmax, cd.Wf,
                               (float)(cd.n_eff - 1), (float)a.min_in_points,
                               a.min_in_points <= 1);
@@ -829,31 +884,37 @@ void search_kernel(SearchArgs a) {
     // slightly relaxed theta; only those that pass get the exact comparison,
     // validity test and index bookkeeping.  The largest box always passes,
     // so the result is that of the full comparison.
-    {
+    //
+    // The relaxation covers the rounding of u = theta R, an FMA chain of k
+    // non-negative terms (relative error below k 2^-24), and for weighted
+    // curves that of the running weight R itself; at least 2^-14.
+    if (kmin <= kscan) {
       const float Wf = cd.Wf;
       const float nmax1 = (float)(cd.n_eff - 1);
       const float mipf = (float)a.min_in_points;
       const bool mip1 = a.min_in_points <= 1;
+      const float margin =
+          fmaxf(0x1p-14f, (float)((WEIGHTED ? 2 : 1) * kscan + 16) * 0x1p-24f);
       int j = tid / np, t = tid - (tid / np) * np;
       const int dj = kBlock / np, dtt = kBlock - (kBlock / np) * np;
       for (; j < nb;) {
         const float theta = __uint_as_float((unsigned)(s_best[t] >> 32));
-        const float thr = theta * (1.0f - 0x1p-14f);
+        const float thr = theta * (1.0f - margin);
         float bn, bd;
         int bm;
         if (WEIGHTED) {
           const float2 *ha = reinterpret_cast<const float2 *>(s_hist) +
                              __umul24((unsigned)t, (unsigned)(2 * HS)) + j;
           const bool need_counts = !(mip1 && s_nonempty[t] > kmax);
-          scan_task_weighted<DIP>(ha, ha + HS, kmin, kmax, Wf, thr, nmax1, mipf, need_counts, bn,
+          scan_task_weighted<DIP>(ha, ha + HS, kmin, kscan, Wf, thr, nmax1, mipf, need_counts, bn,
                                   bd, bm);
         } else {
           const float2 *h =
               reinterpret_cast<const float2 *>(s_hist) + __umul24((unsigned)t, (unsigned)HS) + j;
           if (mip1)
-            scan_task_unit<DIP, true>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
+            scan_task_unit<DIP, true>(h, kmin, kscan, Wf, thr, mipf, bn, bd, bm);
           else
-            scan_task_unit<DIP, false>(h, kmin, kmax, Wf, thr, mipf, bn, bd, bm);
+            scan_task_unit<DIP, false>(h, kmin, kscan, Wf, thr, mipf, bn, bd, bm);
         }
         if (bm >= 0)
           __hip_atomic_fetch_max(&s_best[t], box_key(bn, bd, bm, j, nb), __ATOMIC_RELAXED,
@@ -866,9 +927,29 @@ void search_kernel(SearchArgs a) {
         }
       }
     }
+    // Widths above half the bins (only when kmax allows them): through the
+    // complement, without a screen.
+    if (kmax > kscan) {
+      const int k1lo = nb - kmax;
+      const int k1hi = nb - max(kmin, kscan + 1);
+      const float Stot = (float)cd.Stot;
+      const float neff = (float)cd.n_eff;
+      const float mipf = (float)a.min_in_points;
+      for (int q = tid; q < np * nb; q += kBlock) {
+        const int j1 = q / np, t = q - (q / np) * np;
+        const float2 *h = reinterpret_cast<const float2 *>(s_hist) +
+                          __umul24((unsigned)t, (unsigned)(WEIGHTED ? 2 * HS : HS)) + j1;
+        const unsigned long long key = scan_task_complement<WEIGHTED, DIP>(
+            h, h + HS, j1, k1lo, k1hi, nb, cd.Wf, Stot, neff, mipf);
+        if (key != 0ull)
+          __hip_atomic_fetch_max(&s_best[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
     __syncthreads();
 
-    // Per period: re-sum the winning box in scan order, write the result.
+    // Per period: the winning box's sums again in FP64 from the bins, the
+    // statistic and depth from them.  A box wider than half the bins is
+    // summed through its complement, with the exact totals.
     if (tid < np) {
       const int t = tid;
       const int p = p0 + t;
@@ -884,26 +965,24 @@ void search_kernel(SearchArgs a) {
         const unsigned idx = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
         const int k = (int)(idx / (unsigned)nb);
         const int j = (int)(idx - (unsigned)k * (unsigned)nb);
-        // S in the scan's order; R (exact counts for unit weights)
-        float R = 0.0f, S = 0.0f;
-        if (WEIGHTED) {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist + (size_t)t * HS * 2) + j;
-          for (int m = 0; m < k; ++m) {
-            R += h[m].x;
-            S += h[m].y;
-          }
-        } else {
-          const float2 *h = reinterpret_cast<const float2 *>(s_hist) + (size_t)t * HS + j;
-          for (int m = 0; m < k; ++m) {
-            R += h[m].x;
-            S += h[m].y;
-          }
+        const float2 *plane =
+            reinterpret_cast<const float2 *>(s_hist + (size_t)t * HS * (WEIGHTED ? 2 : 1));
+        const bool wide = 2 * k > nb;
+        const int s0 = wide ? (j + k >= nb ? j + k - nb : j + k) : j;
+        const int len = wide ? nb - k : k;
+        double Rs = 0.0, Ss = 0.0;
+        for (int m = 0; m < len; ++m) {
+          const float2 e = plane[s0 + m];
+          Rs += (double)e.x;
+          Ss += (double)e.y;
         }
-        const double Rd = (double)R;
-        const double den = Rd * ((double)cd.Wf - Rd);
-        const double Sd = (double)S;
-        const double sr = sqrt(Sd * Sd / den) * cd.out_scale;
-        const double depth = -Sd * (double)cd.Wf / den * cd.out_scale;
+        const double W = cd.Wtot;
+        const double R = wide ? W - Rs : Rs;        // weight in the box
+        const double D = wide ? Rs : W - Rs;        // weight outside it
+        const double S = wide ? cd.Stot - Ss : Ss;  // signal in the box
+        const double den = R * D;
+        const double sr = sqrt(S * S / den) * cd.out_scale;
+        const double depth = -S * W / den * cd.out_scale;
         srf = (float)sr;
         a.sr[r] = srf;
         a.depth[r] = (float)depth;

@@ -133,7 +133,11 @@ int cached_read_cycles(int S, int tile, int nbins) {
 
 }  // namespace
 
-int hist_words(int nbins, int kmax) { return nbins + std::max(kmax - 1, 1); }
+int hist_words(int nbins, int kmax) {
+  // widths above nbins / 2 are scanned through their complement, so no
+  // read reaches more than min(kmax, nbins / 2) - 1 bins past the end
+  return nbins + std::max(std::min(kmax, nbins / 2) - 1, 1);
+}
 
 int hist_stride(int nbins, int kmax, int tile, bool weighted) {
   const int hb = hist_words(nbins, kmax);
@@ -359,6 +363,9 @@ void layout_partitions(bls_plan *p, const std::vector<double> &cost,
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out) {
   const int nc = (int)shapes.size();
+  // queued copies (or graph replays) may still read the pinned descriptors
+  const int ws = desc_wait(p);
+  if (ws != BLS_OK) return ws;
   const int wpb = weighted ? 2 : 1;
   out = PlannedBatch{};
   out.ncurves = nc;
@@ -427,9 +434,37 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
   return BLS_OK;
 }
 
-int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
-                   const double *w, const double *periods, float *sr, float *depth, int32_t *js,
-                   int32_t *ks, int64_t *best, bool timed, bool unbinned) {
+int desc_wait(bls_plan *p) {
+  if (!p->desc_pending) return BLS_OK;
+  hipError_t e = hipEventSynchronize(p->ev_desc);
+  if (e != hipSuccess) return hip_error(p, e, "wait for descriptor uploads");
+  p->desc_pending = false;
+  return BLS_OK;
+}
+
+int desc_mark(bls_plan *p) {
+  hipError_t e = hipEventRecord(p->ev_desc, p->stream);
+  if (e != hipSuccess) return hip_error(p, e, "event record");
+  p->desc_pending = true;
+  return BLS_OK;
+}
+
+int ring_begin(bls_plan *p) {
+  const int slot = (int)(p->k_recorded % bls_plan::kTimeRing);
+  hipError_t e = hipEventRecord(p->ev_k0[slot], p->stream);
+  return e == hipSuccess ? BLS_OK : hip_error(p, e, "event record");
+}
+
+int ring_end(bls_plan *p) {
+  const int slot = (int)(p->k_recorded % bls_plan::kTimeRing);
+  hipError_t e = hipEventRecord(p->ev_k1[slot], p->stream);
+  if (e != hipSuccess) return hip_error(p, e, "event record");
+  ++p->k_recorded;
+  return BLS_OK;
+}
+
+int enqueue_pre(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
+                const double *w, const double *periods, int64_t *best) {
   hipStream_t st = p->stream;
   hipError_t e;
   const int nc = pb.ncurves;
@@ -462,7 +497,11 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
   pa.qw = p->d_qw;
   e = (hipError_t)launch_prep(pa, st);
   if (e != hipSuccess) return hip_error(p, e, "launch prep");
+  return BLS_OK;
+}
 
+int enqueue_kernel(bls_plan *p, const PlannedBatch &pb, const double *periods, float *sr,
+                   float *depth, int32_t *js, int32_t *ks, int64_t *best, bool unbinned) {
   SearchArgs sa;
   sa.curves = p->d_curves;
   sa.periods = periods;
@@ -480,27 +519,36 @@ int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const d
   sa.depth = depth;
   sa.jstart = js;
   sa.kwidth = ks;
-  sa.best_key = keys;
+  sa.best_key = reinterpret_cast<unsigned long long *>(best);
   sa.hist_bytes = pb.hist_bytes;
   sa.ucap = pb.ucap;
   sa.nparts = pb.nparts;
   sa.pad_parts = 0;
   for (int x = 0; x <= kMaxParts; ++x) sa.part_begin[x] = pb.part_begin[x];
-  if (timed) {
-    e = hipEventRecord(p->ev_search0, st);
-    if (e != hipSuccess) return hip_error(p, e, "event record");
-  }
   const bool dip = (p->cfg.flags & BLS_DIP_ONLY) != 0;
-  e = unbinned ? (hipError_t)launch_unbinned(sa, pb.weighted, dip, pb.grid, st)
-               : (hipError_t)launch_search(sa, pb.weighted, dip, pb.grid, st);
+  hipError_t e = unbinned ? (hipError_t)launch_unbinned(sa, pb.weighted, dip, pb.grid, p->stream)
+                          : (hipError_t)launch_search(sa, pb.weighted, dip, pb.grid, p->stream);
   if (e != hipSuccess) return hip_error(p, e, "launch search");
-  if (timed) {
-    e = hipEventRecord(p->ev_search1, st);
-    if (e != hipSuccess) return hip_error(p, e, "event record");
-  }
-  e = (hipError_t)launch_best_index(keys, nc, st);
+  return BLS_OK;
+}
+
+int enqueue_post(bls_plan *p, const PlannedBatch &pb, int64_t *best) {
+  hipError_t e = (hipError_t)launch_best_index(reinterpret_cast<unsigned long long *>(best),
+                                               pb.ncurves, p->stream);
   if (e != hipSuccess) return hip_error(p, e, "launch best index");
   return BLS_OK;
+}
+
+int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
+                   const double *w, const double *periods, float *sr, float *depth, int32_t *js,
+                   int32_t *ks, int64_t *best, bool unbinned) {
+  int st = enqueue_pre(p, pb, t, x, w, periods, best);
+  if (st == BLS_OK) st = desc_mark(p);
+  if (st == BLS_OK) st = ring_begin(p);
+  if (st == BLS_OK) st = enqueue_kernel(p, pb, periods, sr, depth, js, ks, best, unbinned);
+  if (st == BLS_OK) st = ring_end(p);
+  if (st == BLS_OK) st = enqueue_post(p, pb, best);
+  return st;
 }
 
 TileChoice default_tiles(bool weighted) {
@@ -520,6 +568,16 @@ TileChoice default_tiles(bool weighted) {
 using namespace bls;
 
 namespace {
+
+// Duration of the most recent bracketed kernel launch (the stream must have
+// reached its end event); 0 if there is none.
+double last_kernel_ms(bls_plan *p) {
+  if (p->k_recorded == 0) return 0.0;
+  const int slot = (int)((p->k_recorded - 1) % bls_plan::kTimeRing);
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, p->ev_k0[slot], p->ev_k1[slot]) != hipSuccess) return 0.0;
+  return ms;
+}
 
 void fill_stats(bls_plan *p, const PlannedBatch &pb, bool replayed) {
   p->stats.trial_points = pb.trial_points;
@@ -606,7 +664,7 @@ int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &
       hipSuccess)
     return hip_error(p, e, "upload periods");
   st = enqueue_search(p, pb, p->d_t, p->d_x, weighted ? p->d_w : nullptr, p->d_periods, p->d_sr,
-                      p->d_depth, p->d_j, p->d_k, p->d_best, true);
+                      p->d_depth, p->d_j, p->d_k, p->d_best);
   if (st != BLS_OK) return st;
   if ((e = hipEventRecord(p->ev_end, s)) != hipSuccess) return hip_error(p, e, "event");
 
@@ -627,8 +685,7 @@ int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &
   if (st != BLS_OK) return st;
 
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1);
-  p->stats.search_ms = ms;
+  p->stats.search_ms = last_kernel_ms(p);
   (void)hipEventElapsedTime(&ms, p->ev_begin, p->ev_end);
   p->stats.total_ms = ms;
   fill_stats(p, pb, false);
@@ -680,11 +737,49 @@ uint64_t batch_signature(const bls_plan *p, const bls_batch &b, const bls_device
 }
 
 void drop_graph(bls_plan *p) {
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
-  p->gexec = nullptr;
-  p->graph = nullptr;
+  for (int g = 0; g < 3; ++g) {
+    if (p->gexec[g]) (void)hipGraphExecDestroy(p->gexec[g]);
+    if (p->graph[g]) (void)hipGraphDestroy(p->graph[g]);
+    p->gexec[g] = nullptr;
+    p->graph[g] = nullptr;
+  }
   p->graph_valid = false;
+}
+
+// Capture one part of the launch sequence into graph g and instantiate it.
+template <class F>
+int capture_part(bls_plan *p, int g, F &&enqueue) {
+  hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_error(p, e, "begin capture");
+  const int st = enqueue();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->stream, &graph);
+  if (st != BLS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_error(p, e, "end capture");
+  p->graph[g] = graph;
+  e = hipGraphInstantiate(&p->gexec[g], graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_error(p, e, "instantiate graph");
+  return BLS_OK;
+}
+
+// Replay the three captured parts, the search kernel between the timing
+// ring's events and the descriptor mark after the uploads.
+int launch_graphs(bls_plan *p) {
+  hipError_t e = hipGraphLaunch(p->gexec[0], p->stream);
+  if (e != hipSuccess) return hip_error(p, e, "graph launch");
+  int st = desc_mark(p);
+  if (st == BLS_OK) st = ring_begin(p);
+  if (st != BLS_OK) return st;
+  if ((e = hipGraphLaunch(p->gexec[1], p->stream)) != hipSuccess)
+    return hip_error(p, e, "graph launch");
+  st = ring_end(p);
+  if (st != BLS_OK) return st;
+  if ((e = hipGraphLaunch(p->gexec[2], p->stream)) != hipSuccess)
+    return hip_error(p, e, "graph launch");
+  return BLS_OK;
 }
 
 }  // namespace
@@ -745,8 +840,12 @@ int bls_plan_create(bls_plan **out, const bls_plan_config *cfg_in) {
       return fail(hip_error(p, e, "create stream"));
     p->own_stream = true;
   }
-  for (hipEvent_t *ev : {&p->ev_begin, &p->ev_search0, &p->ev_search1, &p->ev_end})
+  for (hipEvent_t *ev : {&p->ev_begin, &p->ev_search0, &p->ev_search1, &p->ev_end, &p->ev_desc})
     if ((e = hipEventCreate(ev)) != hipSuccess) return fail(hip_error(p, e, "create event"));
+  for (int i = 0; i < bls_plan::kTimeRing; ++i)
+    if ((e = hipEventCreate(&p->ev_k0[i])) != hipSuccess ||
+        (e = hipEventCreate(&p->ev_k1[i])) != hipSuccess)
+      return fail(hip_error(p, e, "create event"));
 
   const size_t nc = (size_t)cfg.max_curves, npt = (size_t)cfg.max_points;
   struct {
@@ -790,8 +889,12 @@ int bls_plan_destroy(bls_plan *p) {
   for (void *h : {(void *)p->h_curves, (void *)p->h_seg_start, (void *)p->h_seg_curve,
                   (void *)p->h_seg_tile0})
     if (h) (void)hipHostFree(h);
-  for (hipEvent_t ev : {p->ev_begin, p->ev_search0, p->ev_search1, p->ev_end})
+  for (hipEvent_t ev : {p->ev_begin, p->ev_search0, p->ev_search1, p->ev_end, p->ev_desc})
     if (ev) (void)hipEventDestroy(ev);
+  for (int i = 0; i < bls_plan::kTimeRing; ++i) {
+    if (p->ev_k0[i]) (void)hipEventDestroy(p->ev_k0[i]);
+    if (p->ev_k1[i]) (void)hipEventDestroy(p->ev_k1[i]);
+  }
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
   return BLS_OK;
@@ -845,53 +948,49 @@ int bls_search_device(bls_plan *p, const bls_batch *b, const bls_device_results 
   const uint64_t sig = batch_signature(p, *b, *o);
   if (use_graph && p->graph_valid && sig == p->graph_sig) {
     if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
-    if ((e = hipGraphLaunch(p->gexec, p->stream)) != hipSuccess)
-      return hip_error(p, e, "graph launch");
+    int st = launch_graphs(p);
+    if (st != BLS_OK) return st;
     if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
-    p->search_timed = false;
     fill_stats(p, p->last, true);
     return BLS_OK;
   }
   std::string err;
   int st = validate_batch(p->cfg, *b, false, p->shapes, err);
   if (st != BLS_OK) return set_error(p, st, err);
+  if (p->gexec[0]) {
+    // replays of the old graphs may still be queued: let them finish before
+    // their executables go
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_error(p, e, "synchronize");
+    drop_graph(p);
+  }
   const bool weighted = b->weights != nullptr;
   TileChoice tc = choose_tiles(p, p->shapes, weighted);
   PlannedBatch pb;
   st = plan_batch(p, p->shapes, weighted, tc, pb);
   if (st != BLS_OK) return st;
-  drop_graph(p);
   p->last = pb;
   if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   if (use_graph) {
-    if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-      return hip_error(p, e, "begin capture");
-    st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
-                        o->jstart, o->kwidth, o->best_index, false);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+    st = capture_part(p, 0, [&] {
+      return enqueue_pre(p, pb, b->times, b->flux, b->weights, b->periods, o->best_index);
+    });
+    if (st == BLS_OK)
+      st = capture_part(p, 1, [&] {
+        return enqueue_kernel(p, pb, b->periods, o->sr, o->depth, o->jstart, o->kwidth,
+                              o->best_index, false);
+      });
+    if (st == BLS_OK) st = capture_part(p, 2, [&] { return enqueue_post(p, pb, o->best_index); });
+    if (st == BLS_OK) st = launch_graphs(p);
     if (st != BLS_OK) {
-      if (g) (void)hipGraphDestroy(g);
+      drop_graph(p);
       return st;
-    }
-    if (e2 != hipSuccess) return hip_error(p, e2, "end capture");
-    p->graph = g;
-    if ((e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
-      drop_graph(p);
-      return hip_error(p, e, "instantiate graph");
-    }
-    if ((e = hipGraphLaunch(p->gexec, p->stream)) != hipSuccess) {
-      drop_graph(p);
-      return hip_error(p, e, "graph launch");
     }
     p->graph_sig = sig;
     p->graph_valid = true;
-    p->search_timed = false;
   } else {
     st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
-                        o->jstart, o->kwidth, o->best_index, true);
+                        o->jstart, o->kwidth, o->best_index);
     if (st != BLS_OK) return st;
-    p->search_timed = true;
   }
   if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   fill_stats(p, pb, false);
@@ -915,6 +1014,11 @@ int bls_search_unbinned_device(bls_plan *p, const bls_batch *b, const bls_unbinn
   pb.weighted = weighted;
   std::vector<double> cost(nc);
   int ucap = 1;
+  // the pinned descriptors are rewritten: a captured search graph goes
+  // stale, and queued copies may still read them
+  p->graph_valid = false;
+  st = desc_wait(p);
+  if (st != BLS_OK) return st;
   for (int c = 0; c < nc; ++c) {
     const CurveShape &s = p->shapes[c];
     CurveDesc &d = p->h_curves[c];
@@ -955,14 +1059,11 @@ int bls_search_unbinned_device(bls_plan *p, const bls_batch *b, const bls_unbinn
     return hip_error(p, e, "occupancy query");
   if (per_cu < 1) return set_error(p, BLS_ERR_CAPACITY, "unbinned kernel does not fit a CU");
   pb.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)p->num_cus * per_cu));
-  // the pinned descriptors were rewritten: a captured search graph is stale
-  drop_graph(p);
   p->last = pb;
   if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
-                      o->first_point, o->last_point, o->best_index, true, true);
+                      o->first_point, o->last_point, o->best_index, true);
   if (st != BLS_OK) return st;
-  p->search_timed = true;
   if ((e = hipEventRecord(p->ev_end, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   fill_stats(p, pb, false);
   return BLS_OK;
@@ -1252,6 +1353,8 @@ int bls_debug_phase_bins(bls_plan *p, const double *times, int64_t n, double per
   int st = ensure_staging(p);
   if (st != BLS_OK) return st;
   p->graph_valid = false;
+  st = desc_wait(p);
+  if (st != BLS_OK) return st;
   CurveDesc &d = p->h_curves[0];
   memset(&d, 0, sizeof d);
   d.n = n;
@@ -1266,6 +1369,7 @@ int bls_debug_phase_bins(bls_plan *p, const double *times, int64_t n, double per
       (e = hipMemcpyAsync(p->d_t, times, n * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(p->d_periods, &period, 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_error(p, e, "upload");
+  if ((st = desc_mark(p)) != BLS_OK) return st;
   PrepArgs pa;
   pa.curves = p->d_curves;
   pa.periods = p->d_periods;
@@ -1292,10 +1396,8 @@ int bls_synchronize(bls_plan *p) {
   if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_error(p, e, "synchronize");
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, p->ev_begin, p->ev_end) == hipSuccess) p->stats.total_ms = ms;
-  if (p->search_timed && hipEventElapsedTime(&ms, p->ev_search0, p->ev_search1) == hipSuccess)
-    p->stats.search_ms = ms;
-  else
-    p->stats.search_ms = p->stats.total_ms;
+  p->desc_pending = false;
+  p->stats.search_ms = last_kernel_ms(p);
   if (p->last.ncurves > 0) return check_device_status(p, p->last.ncurves);
   return BLS_OK;
 }
@@ -1335,6 +1437,32 @@ const char *bls_status_string(int status) {
 int bls_last_stats(const bls_plan *p, bls_call_stats *out) {
   if (!p || !out) return BLS_ERR_INVALID_ARG;
   *out = p->stats;
+  return BLS_OK;
+}
+
+int bls_kernel_times(bls_plan *p, float *ms, int32_t max, int32_t *count) {
+  if (!p || !count || max < 0 || (max > 0 && !ms)) return BLS_ERR_INVALID_ARG;
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_error(p, e, "set device");
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_error(p, e, "synchronize");
+  const int64_t avail = std::min<int64_t>(p->k_recorded - p->k_base, bls_plan::kTimeRing);
+  const int64_t n = std::min<int64_t>(avail, max);
+  // the most recent n launches, oldest first
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = p->k_recorded - n + i;
+    const int slot = (int)(k % bls_plan::kTimeRing);
+    float v = 0.f;
+    if ((e = hipEventElapsedTime(&v, p->ev_k0[slot], p->ev_k1[slot])) != hipSuccess)
+      return hip_error(p, e, "event timing");
+    ms[i] = v;
+  }
+  *count = (int32_t)n;
+  return BLS_OK;
+}
+
+int bls_kernel_times_reset(bls_plan *p) {
+  if (!p) return BLS_ERR_INVALID_ARG;
+  p->k_base = p->k_recorded;
   return BLS_OK;
 }
 

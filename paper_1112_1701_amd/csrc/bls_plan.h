@@ -90,15 +90,31 @@ struct bls_plan {
   int32_t *h_seg_curve = nullptr;
   int32_t *h_seg_tile0 = nullptr;
 
-  // graph cache for bls_search_device
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // graph cache for bls_search_device: the launch sequence is captured as
+  // three graphs (uploads, fill and prep; the search kernel; the best-index
+  // read-out) so that the search kernel's own duration can be bracketed by
+  // events on every replay
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   uint64_t graph_sig = 0;
   bool graph_valid = false;
 
   hipEvent_t ev_begin = nullptr, ev_search0 = nullptr, ev_search1 = nullptr,
              ev_end = nullptr;
-  bool search_timed = false;
+
+  // The pinned descriptors above are read by queued copies (or graph
+  // replays) until ev_desc, recorded after them, completes; a call that
+  // rewrites them first waits for it.
+  hipEvent_t ev_desc = nullptr;
+  bool desc_pending = false;
+
+  // Search-kernel durations of the last kTimeRing calls: events recorded
+  // just before and after each search (or unbinned) kernel launch.
+  static constexpr int kTimeRing = 64;
+  hipEvent_t ev_k0[kTimeRing] = {};
+  hipEvent_t ev_k1[kTimeRing] = {};
+  int64_t k_recorded = 0;   // kernel launches bracketed so far
+  int64_t k_base = 0;       // value of k_recorded at the last reset
 
   bls::PlannedBatch last;
   bls_call_stats stats{};
@@ -128,12 +144,28 @@ void layout_partitions(bls_plan *p, const std::vector<double> &cost,
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out);
 
-// Queue: upload descriptors, clear counters, prep, search, best index.
-// With unbinned, the unbinned kernel replaces the search kernel (js and ks
-// then receive the first and last point of each best box).
+// The launch sequence of a search, in three parts: (1) upload descriptors,
+// clear counters and keys, prep; (2) the search kernel (with unbinned, the
+// unbinned kernel: js and ks then receive the first and last point of each
+// best box); (3) per-curve best index.  Nothing here records events, so each
+// part can be captured into a graph.
+int enqueue_pre(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
+                const double *w, const double *periods, int64_t *best);
+int enqueue_kernel(bls_plan *p, const PlannedBatch &pb, const double *periods, float *sr,
+                   float *depth, int32_t *js, int32_t *ks, int64_t *best, bool unbinned);
+int enqueue_post(bls_plan *p, const PlannedBatch &pb, int64_t *best);
+// All three, with ev_desc after the uploads and the kernel bracketed by the
+// timing ring's events (streams that are not capturing).
 int enqueue_search(bls_plan *p, const PlannedBatch &pb, const double *t, const double *x,
                    const double *w, const double *periods, float *sr, float *depth,
-                   int32_t *js, int32_t *ks, int64_t *best, bool timed, bool unbinned = false);
+                   int32_t *js, int32_t *ks, int64_t *best, bool unbinned = false);
+// Wait until no queued copy or graph still reads the pinned descriptors.
+int desc_wait(bls_plan *p);
+// Mark the pinned descriptors as read by work queued so far on the stream.
+int desc_mark(bls_plan *p);
+// Events of the timing ring around the next kernel launch.
+int ring_begin(bls_plan *p);
+int ring_end(bls_plan *p);
 
 int set_error(bls_plan *p, int status, const std::string &msg);
 int hip_error(bls_plan *p, hipError_t e, const char *what);
@@ -143,7 +175,7 @@ int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t 
 hipError_t device_alloc(void **ptr, size_t bytes);
 
 // LDS words (64-bit) one period's histogram plane needs: the bins, then the
-// clamp word / wrap-around copy of the first kmax - 1 bins.
+// clamp word / wrap-around copy of the first min(kmax, nbins / 2) - 1 bins.
 int hist_words(int nbins, int kmax);
 // Words between consecutive periods' planes for a tile of `tile` periods:
 // at least hist_words, padded so that the scan's 64-bit reads, served 16

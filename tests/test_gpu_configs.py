@@ -153,12 +153,16 @@ def test_uneven_batch_full_size(bls):
 
 
 def test_long_baseline_full_size(bls):
-    """256 curves x N = 50000 on a 1-minute grid, 100000 periods, 1000 bins."""
+    """256 curves x N = 50000 on a 1-minute grid, 100000 periods, 1000 bins:
+    two whole periodograms (every period, the box rule and the best index)
+    and 200 sampled (curve, period) pairs against the oracle."""
     b = synth.config4()
     _say("long baseline full size")
     outs, st = _run_device(bls, b)
+    curves = [0, 255]
+    rels, mism = _full_curves(b, outs, curves, "long")
     r2, m2 = _sampled_pairs(b, outs, np.random.default_rng(3), 200, "long")
-    _report("long", st, r2, m2, 200, [])
+    _report("long", st, rels + r2, mism + m2, 200, curves)
     # the injected period (or an alias) is found for most curves
     import torch
     bi = outs[4].cpu().numpy()
