@@ -185,6 +185,40 @@ typedef struct {
 int bls_search_device(bls_plan *plan, const bls_batch *batch,
                       const bls_device_results *out);
 
+/*
+ * bls_search_device for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  No plan: the call allocates nothing (no hipMalloc or hipFree,
+ * no pinned or heap host memory) and works in a fixed scratch array that
+ * the library holds in each GPU's memory until the process ends
+ * (BLS_NOALLOC_SCRATCH_BYTES per GPU: prepared points, curve descriptors,
+ * work segments and counters).
+ *   batch: as for bls_search_device (times, flux, weights, periods on the
+ *   current HIP device; n_off, p_off, nbins, qmin, qmax host arrays), at most
+ *   BLS_NOALLOC_MAX_CURVES curves and BLS_NOALLOC_MAX_POINTS points in all,
+ *   nbins <= BLS_MAX_NBINS.
+ *   out: as for bls_search_device.
+ *   flags: BLS_DIP_ONLY or 0; min_in_points >= 1 (as a plan's).
+ *   hip_stream: the hipStream_t to queue on (NULL: the default stream).
+ * Runs on the calling thread's current HIP device, asynchronously on
+ * hip_stream, with the built-in tile table (no tuning); results equal
+ * bls_search_device's.  A curve whose data is invalid gets SR = NaN and
+ * jstart = kwidth = -1 (nothing is read back to report it).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents: calls queued on one stream run one after the other,
+ * calls on different streams (or threads) that overlap on one GPU race.
+ * Errors, checked on the host before anything is queued (message via
+ * bls_last_error(NULL, ...)): INVALID_ARG (as bls_search_device, or flags),
+ * CAPACITY (more curves or points than the limits above, a histogram that
+ * does not fit a workgroup's LDS), DEVICE.
+ */
+#define BLS_NOALLOC_MAX_CURVES 64
+#define BLS_NOALLOC_MAX_POINTS (1 << 20)
+#define BLS_NOALLOC_SCRATCH_BYTES (16u * (1u << 20) + 16384u)
+int bls_search_device_noalloc(const bls_batch *batch,
+                              const bls_device_results *out, uint32_t flags,
+                              int32_t min_in_points, void *hip_stream);
+
 /* Wait for the plan's queued work.  Returns INVALID_ARG if a curve of the
  * last bls_search_device call had invalid data (message names the first
  * such curve), DEVICE on a HIP error. */

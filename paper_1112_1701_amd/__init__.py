@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     bls_search,
     bls_search_batch,
     bls_search_device,
+    bls_search_device_noalloc,
     bls_synchronize,
     bls_get_stream,
     bls_width_range,
@@ -45,4 +46,5 @@ from ._lib import (  # noqa: F401
     BLS_OK, BLS_ERR_INVALID_ARG, BLS_ERR_NO_MEMORY, BLS_ERR_DEVICE,
     BLS_ERR_CAPACITY, BLS_ERR_BUSY, BLS_ERR_TIMEOUT, BLS_DIP_ONLY,
     BLS_NO_GRAPH, BLS_NO_AUTOTUNE, BLS_MAX_NBINS, LIB_PATH,
+    BLS_NOALLOC_MAX_CURVES, BLS_NOALLOC_MAX_POINTS, BLS_NOALLOC_SCRATCH_BYTES,
 )

@@ -23,6 +23,9 @@ BLS_DIP_ONLY = 1 << 0
 BLS_NO_GRAPH = 1 << 1
 BLS_NO_AUTOTUNE = 1 << 2
 BLS_MAX_NBINS = 4096
+BLS_NOALLOC_MAX_CURVES = 64
+BLS_NOALLOC_MAX_POINTS = 1 << 20
+BLS_NOALLOC_SCRATCH_BYTES = 16 * (1 << 20) + 16384
 
 
 class BlsPlanConfig(C.Structure):
@@ -177,6 +180,7 @@ def load():
         "bls_eclipse_window_device": (C.c_int, [P, P, I32, D, I32, P]),
         "bls_variability_device": (C.c_int, [P, P, P, P]),
         "bls_search_unbinned_device": (C.c_int, [P, P, P]),
+        "bls_search_device_noalloc": (C.c_int, [P, P, C.c_uint32, I32, P]),
     }
     optional = {
         "bls_server_config_init": (None, [P]),

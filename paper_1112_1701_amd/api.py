@@ -227,6 +227,26 @@ def bls_search_device(plan, n_off, times, flux, weights, periods, p_off,
            plan)
 
 
+def bls_search_device_noalloc(n_off, times, flux, weights, periods, p_off,
+                              nbins, qmin, qmax, sr, depth, jstart, kwidth,
+                              best_index, flags=0, min_in_points=1,
+                              stream=None):
+    """bls_search_device without a plan: allocates nothing, works in the
+    library's fixed per-GPU scratch array; asynchronous on `stream` (a
+    torch.cuda.Stream, a raw hipStream_t as int, or None for the default
+    stream) of the current device.  Synchronize the stream before reading.
+    """
+    ba = _batch(n_off, times, flux, weights, periods, p_off, nbins, qmin,
+                qmax, device=True)
+    o = L.BlsDeviceResults(sr.data_ptr(), depth.data_ptr(), jstart.data_ptr(),
+                           kwidth.data_ptr(), best_index.data_ptr())
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(L.load().bls_search_device_noalloc(
+        C.byref(ba.struct), C.byref(o), int(flags), int(min_in_points),
+        C.c_void_p(stream) if stream else None))
+
+
 def bls_search_unbinned_device(plan, n_off, times, flux, weights, periods,
                                p_off, qmin, qmax, sr, depth, first_point,
                                last_point, best_index):

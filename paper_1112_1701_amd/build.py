@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbls_mi355x.so")
 
 SOURCES = ["bls_kernels.hip", "bls_plan.cpp", "bls_autotune.cpp",
-           "bls_server.cpp"]
+           "bls_server.cpp", "bls_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -22,7 +22,10 @@
 namespace bls {
 namespace {
 
-thread_local std::string g_create_error;
+// Message of the calling thread's last error without a plan (plan creation,
+// the plan-free search); a fixed buffer, so that recording it allocates
+// nothing.
+thread_local char g_create_error[256];
 std::atomic<long long> g_alloc_count{0};
 
 uint64_t fnv1a(uint64_t h, const void *data, size_t bytes) {
@@ -66,7 +69,12 @@ int set_error(bls_plan *p, int status, const std::string &msg) {
   if (p)
     p->last_error = msg;
   else
-    g_create_error = msg;
+    snprintf(g_create_error, sizeof g_create_error, "%s", msg.c_str());
+  return status;
+}
+
+int set_error_noplan(int status, const char *msg) {
+  snprintf(g_create_error, sizeof g_create_error, "%s", msg);
   return status;
 }
 
@@ -139,12 +147,13 @@ int hist_words(int nbins, int kmax) {
   return nbins + std::max(std::min(kmax, nbins / 2) - 1, 1);
 }
 
-int hist_stride(int nbins, int kmax, int tile, bool weighted) {
+int hist_stride(int nbins, int kmax, int tile, bool weighted, bool memo) {
   const int hb = hist_words(nbins, kmax);
   const int wpb = weighted ? 2 : 1;  // the scan reads the first plane of wpb
   int best = hb, best_cost = 0;
   for (int hs = hb; hs < hb + 16; ++hs) {
-    const int c = cached_read_cycles(hs * wpb, tile, nbins);
+    const int c = memo ? cached_read_cycles(hs * wpb, tile, nbins)
+                       : scan_read_cycles((hs * wpb) & 15, tile, std::min(nbins, 4 * kBlock));
     if (hs == hb || c < best_cost) {
       best = hs;
       best_cost = c;
@@ -154,23 +163,61 @@ int hist_stride(int nbins, int kmax, int tile, bool weighted) {
 }
 
 void fit_tile(int nbins, int kmax, int64_t nperiods, int lds_budget, int tile_cap,
-              bool weighted, int *tile, int *stride) {
+              bool weighted, int *tile, int *stride, bool memo) {
   const int wpb = weighted ? 2 : 1;
   int T = std::max(1, lds_budget / (hist_words(nbins, kmax) * 8 * wpb));
   T = std::min(T, std::min(tile_cap, kTileMax));
   T = (int)std::min<int64_t>(T, std::max<int64_t>(nperiods, 1));
   T = std::max(T, 1);
-  int hs = hist_stride(nbins, kmax, T, weighted);
+  int hs = hist_stride(nbins, kmax, T, weighted, memo);
   while (T > 1 && T * hs * 8 * wpb > lds_budget) {
     --T;
-    hs = hist_stride(nbins, kmax, T, weighted);
+    hs = hist_stride(nbins, kmax, T, weighted, memo);
   }
   *tile = T;
   *stride = hs;
 }
 
-int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
-                   std::vector<CurveShape> &shapes, std::string &err, bool binned) {
+namespace {
+// Message sink of validate_batch_into: a caller-owned character buffer.
+struct ErrBuf {
+  char *buf;
+  size_t len;
+  ErrBuf &operator=(const char *m) {
+    if (buf && len) snprintf(buf, len, "%s", m);
+    return *this;
+  }
+};
+}  // namespace
+
+void fill_curve_desc(const CurveShape &s, bool weighted, const TileChoice &tc,
+                     bool check_periods, bool memo, CurveDesc &d) {
+  memset(&d, 0, sizeof d);
+  d.n_off = s.n_off;
+  d.n = s.n;
+  d.p_off = s.p_off;
+  d.r_off = s.r_off;
+  d.nperiods = s.nperiods;
+  d.nbins = s.nbins;
+  d.kmin = s.kmin;
+  d.kmax = s.kmax;
+  const int cb = cbits_of(s.n);
+  d.shift = 64 - cb;
+  d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
+  d.weighted = weighted ? 1 : 0;
+  d.check_periods = check_periods ? 1 : 0;
+  // bins, then the clamp word / wrap-around copy, per period and plane,
+  // padded against LDS bank conflicts, as the kernel lays them out
+  int T = 1, hs = 0;
+  fit_tile(s.nbins, s.kmax, s.nperiods, tc.lds_budget, tc.tile_cap, weighted, &T, &hs, memo);
+  d.tile = T;
+  d.hstride = hs;
+}
+
+int validate_batch_into(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
+                        CurveShape *shapes, int shapes_cap, char *err_buf, size_t err_len,
+                        bool binned) {
+  ErrBuf err{err_buf, err_len};
   char msg[256];
   if (b.ncurves < 1 || b.n_off == nullptr || b.times == nullptr || b.flux == nullptr ||
       b.periods == nullptr) {
@@ -195,7 +242,10 @@ int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_da
     err = "p_off[0] must be 0";
     return BLS_ERR_INVALID_ARG;
   }
-  shapes.resize(b.ncurves);
+  if (shapes_cap < b.ncurves) {
+    err = "shape buffer smaller than the batch";
+    return BLS_ERR_CAPACITY;
+  }
   int64_t total_results = 0;
   for (int c = 0; c < b.ncurves; ++c) {
     CurveShape &s = shapes[c];
@@ -323,6 +373,16 @@ int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_da
   return BLS_OK;
 }
 
+int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
+                   std::vector<CurveShape> &shapes, std::string &err, bool binned) {
+  if (b.ncurves >= 1 && b.ncurves <= cfg.max_curves) shapes.resize(b.ncurves);
+  char buf[256] = "";
+  const int st = validate_batch_into(cfg, b, check_data, shapes.data(), (int)shapes.size(), buf,
+                                     sizeof buf, binned);
+  if (st != BLS_OK) err = buf;
+  return st;
+}
+
 // Segments of the batch, grouped by work partition.  Curves go to the
 // partitions round-robin in descending cost, so each partition (one per XCD:
 // the device dispatches workgroups to its XCDs round-robin) gets a similar
@@ -377,28 +437,10 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
   for (int c = 0; c < nc; ++c) {
     const CurveShape &s = shapes[c];
     CurveDesc &d = p->h_curves[c];
-    memset(&d, 0, sizeof d);
-    d.n_off = s.n_off;
-    d.n = s.n;
-    d.p_off = s.p_off;
-    d.r_off = s.r_off;
-    d.nperiods = s.nperiods;
-    d.nbins = s.nbins;
-    d.kmin = s.kmin;
-    d.kmax = s.kmax;
-    const int cb = cbits_of(s.n);
-    d.shift = 64 - cb;
-    d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
-    d.weighted = weighted ? 1 : 0;
     // each distinct period range is checked once (a shared grid by curve 0)
-    d.check_periods = (c == 0 || s.p_off != shapes[0].p_off) ? 1 : 0;
-    // bins, then the clamp word / wrap-around copy, per period and plane,
-    // padded against LDS bank conflicts, as the kernel lays them out
-    int T = 1, hs = 0;
-    fit_tile(s.nbins, s.kmax, s.nperiods, tc.lds_budget, tc.tile_cap, weighted, &T, &hs);
-    d.tile = T;
-    d.hstride = hs;
-    hist_bytes = std::max(hist_bytes, T * hs * 8 * wpb);
+    fill_curve_desc(s, weighted, tc, c == 0 || s.p_off != shapes[0].p_off, true, d);
+    const int T = d.tile;
+    hist_bytes = std::max(hist_bytes, T * d.hstride * 8 * wpb);
     const double nw = (double)(s.kmax - s.kmin + 1);
     item_cost[c] = (double)T * ((double)s.n + 1.6 * (double)s.nbins * nw);
     out.total_points += s.n;
@@ -823,7 +865,7 @@ int bls_plan_create(bls_plan **out, const bls_plan_config *cfg_in) {
   p->cfg = cfg;
   p->device = cfg.device;
   auto fail = [&](int st) {
-    g_create_error = p->last_error;
+    snprintf(g_create_error, sizeof g_create_error, "%s", p->last_error.c_str());
     bls_plan_destroy(p);
     return st;
   };
@@ -1414,9 +1456,9 @@ int bls_width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int3
 
 int bls_last_error(const bls_plan *p, char *buf, size_t len) {
   if (!buf || len == 0) return BLS_ERR_INVALID_ARG;
-  const std::string &m = p ? p->last_error : g_create_error;
-  const size_t n = std::min(len - 1, m.size());
-  memcpy(buf, m.data(), n);
+  const char *m = p ? p->last_error.c_str() : g_create_error;
+  const size_t n = std::min(len - 1, strlen(m));
+  memcpy(buf, m, n);
   buf[n] = '\0';
   return BLS_OK;
 }

@@ -134,6 +134,17 @@ namespace bls {
 // phase limits (0 < qmin <= qmax < 1) with at most kUnbinnedMaxPoints points.
 int validate_batch(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
                    std::vector<CurveShape> &shapes, std::string &err, bool binned = true);
+// The same into caller-owned storage (no heap use): shapes has room for
+// shapes_cap curves; a failure's message goes to err (NUL-terminated).
+int validate_batch_into(const bls_plan_config &cfg, const bls_batch &b, bool check_data,
+                        CurveShape *shapes, int shapes_cap, char *err, size_t err_len,
+                        bool binned = true);
+// Host fields of one curve's descriptor (prep fields zero): fixed-point
+// layout, and the period tile and plane stride that fit tc's LDS budget.
+// memo: keep the bank-conflict costs of plane strides in the process-wide
+// cache (false: compute them afresh, with no heap use).
+void fill_curve_desc(const CurveShape &s, bool weighted, const TileChoice &tc,
+                     bool check_periods, bool memo, CurveDesc &d);
 
 // Segments grouped into work partitions (one per XCD), curves assigned
 // round-robin in descending cost; items_of[c] = work items of curve c.
@@ -168,6 +179,9 @@ int ring_begin(bls_plan *p);
 int ring_end(bls_plan *p);
 
 int set_error(bls_plan *p, int status, const std::string &msg);
+// The calling thread's error without a plan (what bls_last_error(NULL)
+// returns), recorded without heap use.
+int set_error_noplan(int status, const char *msg);
 int hip_error(bls_plan *p, hipError_t e, const char *what);
 int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t *kmax);
 
@@ -181,11 +195,11 @@ int hist_words(int nbins, int kmax);
 // at least hist_words, padded so that the scan's 64-bit reads, served 16
 // lanes at a time across 32 four-byte banks, meet as few bank conflicts as
 // the layout allows (lane task (start bin, period) = divmod(lane, tile)).
-int hist_stride(int nbins, int kmax, int tile, bool weighted);
+int hist_stride(int nbins, int kmax, int tile, bool weighted, bool memo = true);
 // Periods per work item that fit an LDS budget (at least one, at most
 // tile_cap and nperiods) and the padded stride that goes with it.
 void fit_tile(int nbins, int kmax, int64_t nperiods, int lds_budget, int tile_cap,
-              bool weighted, int *tile, int *stride);
+              bool weighted, int *tile, int *stride, bool memo = true);
 
 // Tile choice for a batch: autotuned (cached) unless disabled.
 TileChoice choose_tiles(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted);

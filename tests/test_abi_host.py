@@ -110,6 +110,26 @@ def test_status_strings(lib):
     assert bls.bls_status_string(-99) == "unknown status"
 
 
+def test_noalloc_without_device_fails_cleanly(lib):
+    """The plan-free search checks its arguments on the host, then needs a
+    current device; without one it fails with a status, not a crash."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1112_1701_amd as bls
+    from paper_1112_1701_amd import _lib as L
+    b = L.BlsBatch()
+    o = L.BlsDeviceResults()
+    assert lib.bls_search_device_noalloc(None, None, 0, 1, None) == \
+        bls.BLS_ERR_INVALID_ARG
+    o.sr = o.depth = o.jstart = o.kwidth = o.best_index = 8
+    assert lib.bls_search_device_noalloc(C.byref(b), C.byref(o), 1 << 5, 1,
+                                         None) == bls.BLS_ERR_INVALID_ARG
+    assert "flags" in bls.bls_last_error(None)
+    assert lib.bls_search_device_noalloc(C.byref(b), C.byref(o), 0, 1,
+                                         None) == bls.BLS_ERR_DEVICE
+
+
 def test_plan_create_without_device_fails_cleanly(lib):
     import torch
     if torch.cuda.is_available():
