@@ -77,6 +77,11 @@ def _load():
         ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
         P, P, P, P, P]
     lib.bls_oracle_unbinned.restype = ctypes.c_int
+    lib.bls_oracle_inject.argtypes = [
+        P, P, ctypes.c_int64, P, ctypes.c_int32, P, P, P, P, P]
+    lib.bls_oracle_inject.restype = ctypes.c_int
+    lib.bls_oracle_recovered.argtypes = [ctypes.c_double] * 5
+    lib.bls_oracle_recovered.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -279,3 +284,58 @@ def unbinned(t, x, w, periods, qmin, qmax, *, min_in_points=1,
         raise OracleError("oracle rejected the input (status %d)" % st)
     return dict(sr=sr, depth=depth, first=first, last=last,
                 best_index=int(best.value))
+
+
+def inject(t, w, base, period, phase, q, depth) -> np.ndarray:
+    """Box eclipses injected into copies of one cadence (readings I1-I3 of
+    bls_oracle.c); base: [ninj, n] fluxes before injection.  Returns the
+    injected fluxes [ninj, n]."""
+    lib = _load()
+    t = _f64(t)
+    w = None if w is None else _f64(w)
+    n = t.shape[0]
+    base = _f64(base).reshape(-1, n)
+    ninj = base.shape[0]
+    prm = [_f64(np.broadcast_to(v, (ninj,))) for v in (period, phase, q, depth)]
+    out = np.empty((ninj, n), np.float64)
+    st = lib.bls_oracle_inject(_ptr(t), _ptr(w), n, _ptr(base), ninj,
+                               *[_ptr(v) for v in prm], _ptr(out))
+    if st != 0:
+        raise OracleError("oracle rejected the input (status %d)" % st)
+    return out
+
+
+def recovered(best_period, sde, p_inj, sde_threshold, ptol) -> bool:
+    """Recovery rule I4 of bls_oracle.c."""
+    return bool(_load().bls_oracle_recovered(
+        float(best_period), float(sde), float(p_inj), float(sde_threshold),
+        float(ptol)))
+
+
+def recovery(t, w, base, period, phase, q, depth, periods, nbins, qmin, qmax,
+             *, window=0.01, sde_threshold=7.0, ptol=0.01, nthreads=0,
+             which=None):
+    """Injection-recovery of one cadence: inject, search each copy over the
+    trial grid, take its detection statistics, apply rule I4.
+
+    which: indices of the injections to run (all by default).  Returns a dict
+    of arrays over those injections: recovered (int), best_index, sde, and
+    the oracle results (list of OracleResult) and injected fluxes."""
+    x = inject(t, w, base, period, phase, q, depth)
+    ninj = x.shape[0]
+    idx = np.arange(ninj) if which is None else np.asarray(which)
+    pr = _f64(np.broadcast_to(period, (ninj,)))
+    periods = _f64(periods)
+    rec, best, sdes, res = [], [], [], []
+    for i in idx:
+        o = search(t, x[i], w, periods, nbins, qmin, qmax, nthreads=nthreads)
+        d = detect(o.sr, periods, max_peaks=1, window=window,
+                   threshold=sde_threshold)
+        rec.append(int(recovered(periods[o.best_index], d["sde"], pr[i],
+                                 sde_threshold, ptol)))
+        best.append(o.best_index)
+        sdes.append(d["sde"])
+        res.append(o)
+    return dict(recovered=np.array(rec, np.int32),
+                best_index=np.array(best, np.int64), sde=np.array(sdes),
+                results=res, flux=x[idx])

@@ -867,3 +867,69 @@ int bls_oracle_unbinned(const double *t, const double *x, const double *w,
     free_kept(&kc);
     return failed ? BLS_ORACLE_NOMEM : BLS_ORACLE_OK;
 }
+
+/*
+ * Injection of box eclipses into copies of one cadence, and the recovery
+ * rule: the paper's detection-efficiency simulations (section 5, Discussion
+ * and conclusions: eclipses of a binary of given period on the real
+ * cadences) taken through the search itself.  Readings:
+ *   I1  the phase origin is t0 = min kept time (weight > 0; all points with
+ *       a NULL weight array), as for the search; d = t - t0;
+ *   I2  injection i (period P, start phase phi in [0, 1), duty cycle q,
+ *       depth delta) covers the points with frac(d / P - phi) < q, in the
+ *       FP64 order f = 1/P, c = d f, u = c - phi, v = u - floor(u);
+ *   I3  an injected point's flux is base - delta, every other point keeps
+ *       base (dropped points too: the search ignores them);
+ *   I4  an injection is recovered when its periodogram's detection
+ *       statistic SDE is at least the threshold and its best period P_b
+ *       (first period of largest SR) lies within ptol h P of h P for h in
+ *       {1, 1/2, 2} (the injected period or its first aliases).
+ */
+int bls_oracle_inject(const double *t, const double *w, int64_t n,
+                      const double *base, int32_t ninj, const double *period,
+                      const double *phase, const double *q,
+                      const double *depth, double *x)
+{
+    if (n < 1 || ninj < 1 || !t || !base || !period || !phase || !q ||
+        !depth || !x)
+        return BLS_ORACLE_INVALID;
+    double t0 = INFINITY;
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (w && !(w[i] > 0.0))
+            continue;
+        if (t[i] < t0)
+            t0 = t[i];
+        ++kept;
+    }
+    if (kept == 0)
+        return BLS_ORACLE_INVALID;
+    for (int32_t k = 0; k < ninj; ++k) {
+        const double f = 1.0 / period[k];
+        const double *b = base + (int64_t)k * n;
+        double *o = x + (int64_t)k * n;
+        for (int64_t i = 0; i < n; ++i) {
+            const int keep = !w || w[i] > 0.0;
+            const double d = t[i] - t0;
+            const double c = d * f;
+            const double u = c - phase[k];
+            const double v = u - floor(u);
+            o[i] = (keep && v < q[k]) ? b[i] - depth[k] : b[i];
+        }
+    }
+    return BLS_ORACLE_OK;
+}
+
+int bls_oracle_recovered(double best_period, double sde, double p_inj,
+                         double sde_threshold, double ptol)
+{
+    if (!(sde >= sde_threshold))
+        return 0;
+    static const double h[3] = {1.0, 0.5, 2.0};
+    for (int i = 0; i < 3; ++i) {
+        const double target = h[i] * p_inj;
+        if (fabs(best_period - target) <= ptol * target)
+            return 1;
+    }
+    return 0;
+}

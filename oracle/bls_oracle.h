@@ -140,6 +140,22 @@ int bls_oracle_unbinned(const double *t, const double *x, const double *w,
                         double *depth, int32_t *first_point,
                         int32_t *last_point, int64_t *best_index);
 
+/*
+ * Box eclipses injected into copies of one cadence (readings I1-I3 in
+ * bls_oracle.c).  t, w: [n] (w may be NULL); base: [ninj * n] fluxes before
+ * injection, injection-major; period, phase, q, depth: [ninj].  x: [ninj * n]
+ * output.  Returns BLS_ORACLE_OK, or BLS_ORACLE_INVALID (no kept point).
+ */
+int bls_oracle_inject(const double *t, const double *w, int64_t n,
+                      const double *base, int32_t ninj, const double *period,
+                      const double *phase, const double *q,
+                      const double *depth, double *x);
+
+/* Recovery rule I4: 1 when sde >= sde_threshold and best_period is within
+ * ptol h p_inj of h p_inj for some h in {1, 1/2, 2}, else 0. */
+int bls_oracle_recovered(double best_period, double sde, double p_inj,
+                         double sde_threshold, double ptol);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,4 +24,6 @@ from .lightcurves import (  # noqa: F401
     cadence_batch,
     variability_field,
     detection_periodograms,
+    InjectionSet,
+    injection_set,
 )

@@ -416,3 +416,45 @@ def detection_periodograms(seed: int = _BASE_SEED + 9):
     # All SR equal and positive: std 0, sde 0, peaks by index only.
     cases.append((np.full(700, 0.25), np.linspace(1.0, 2.0, 700), 5, 0.0))
     return cases
+
+
+@dataclass
+class InjectionSet:
+    """One cadence, its per-injection flux realizations and box eclipses,
+    and the trial grid of the search (inputs of the injection-recovery)."""
+    t: np.ndarray            # [n] cadence times
+    w: Optional[np.ndarray]  # [n] weights or None
+    base: np.ndarray         # [ninj, n] fluxes before injection
+    period: np.ndarray       # [ninj] injected period (d)
+    phase: np.ndarray        # [ninj] start phase in [0, 1)
+    q: np.ndarray            # [ninj] duty cycle
+    depth: np.ndarray        # [ninj] depth (flux units)
+    periods: np.ndarray      # [nperiods] trial grid
+    nbins: int
+    qmin: float
+    qmax: float
+
+
+def injection_set(ninj: int = 4096, seed: int = _BASE_SEED + 10,
+                  nperiods: int = 20000, nbins: int = 300,
+                  sigma: float = 0.01, depth_range=(0.003, 0.03),
+                  q_range=(0.01, 0.05), period_range=(0.3, 10.0),
+                  weighted: bool = False, nights: int = 60) -> InjectionSet:
+    """Box eclipses of log-uniform period, random phase, duty cycle and depth
+    in copies of one survey cadence, each with its own Gaussian noise."""
+    rng = np.random.default_rng(seed)
+    t = survey_cadence(rng, nights=nights)
+    n = t.shape[0]
+    w = None
+    if weighted:
+        w = 1.0 / (sigma * rng.uniform(0.8, 1.2, n)) ** 2
+        w[rng.random(n) < 0.03] = 0.0           # a few rejected exposures
+    lo, hi = np.log(period_range[0]), np.log(period_range[1])
+    period = np.exp(rng.uniform(lo, hi, ninj))
+    phase = rng.uniform(0.0, 1.0, ninj)
+    q = rng.uniform(*q_range, ninj)
+    depth = rng.uniform(*depth_range, ninj)
+    base = 1.0 + sigma * rng.standard_normal((ninj, n))
+    return InjectionSet(t, w, base, period, phase, q, depth,
+                        log_period_grid(0.2, 10.0, nperiods), nbins, 0.01,
+                        0.10)
