@@ -28,6 +28,9 @@ workloads, each with its kernel time, roofline and oracle.
 --copy-calibration: three plain device copies of 1 GiB and nothing else,
 the reference run that scales the HBM traffic counters (FETCH_SIZE,
 WRITE_SIZE) to bytes.
+
+--probes: micro-benchmarks of LDS atomic and read rates and VALU issue rates
+(libbls_probes.so), the measured basis of the kernel design notes.
 """
 from __future__ import annotations
 
@@ -730,6 +733,73 @@ def suite_detect(args, bls):
             "cpu_baseline": cpu}
 
 
+def suite_recovery(args, bls):
+    """Injection-recovery: 4096 box eclipses injected into copies of one
+    survey cadence, each copy searched over 20000 trial periods with its
+    detection statistics, recovered fraction per injected-period decade."""
+    import numpy as np
+    import torch
+
+    import synth
+    log("suite recovery")
+    s = synth.injection_set(4096)
+    ninj, n = s.base.shape
+    m = s.periods.size
+    dev = torch.device("cuda:0")
+    t = torch.tensor(s.t, device=dev)
+    base = torch.tensor(s.base, device=dev)
+    per = torch.tensor(s.periods, device=dev)
+    thr, ptol = 7.0, 0.01
+    with bls.Plan(max_curves=ninj, max_points=ninj * n,
+                  max_periods=ninj * m) as p:
+        kms, wall = [], []
+        for r in range(args.suite_steps + 1):
+            t0 = time.perf_counter()
+            res = bls.bls_injection_recovery_device(
+                p.handle, t, None, base, s.period, s.phase, s.q, s.depth,
+                per, s.nbins, s.qmin, s.qmax, sde_threshold=thr, ptol=ptol)
+            wall.append((time.perf_counter() - t0) * 1e3)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+        st = bls.bls_last_stats(p.handle)
+    k_ms, w_ms = _median(kms[1:]), _median(wall[1:])
+    pp, evals = st["trial_points"], st["box_evals"]
+    edges = [0.3, 1.0, 3.0, 10.0]
+    frac = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (s.period >= lo) & (s.period < hi)
+        frac.append({"period_d": [lo, hi], "injections": int(sel.sum()),
+                     "recovered_frac": float(np.mean(res["recovered"][sel]
+                                                     == 1))})
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_budget / 3 and k < ninj:
+            oracle.recovery(s.t, None, s.base[k:k + 1], s.period[k],
+                            s.phase[k], s.q[k], s.depth[k], s.periods,
+                            s.nbins, s.qmin, s.qmax, sde_threshold=thr,
+                            ptol=ptol)
+            k += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": k / el, "unit": "injections/s",
+               "cores": os.cpu_count(), "kind": "oracle",
+               "sample": "first %d injections, all periods" % k}
+    return {"workload": "injection-recovery: 4096 box eclipses (P 0.3-10 d "
+                        "log-uniform, q 0.01-0.05, depth 0.003-0.03, noise "
+                        "0.01) in copies of one %d-epoch survey cadence, "
+                        "20000 log periods 0.2-10 d, nbins=300, SDE >= 7, "
+                        "period within 1%% (or half/double)" % n,
+            "injections": ninj, "trial_points": pp, "box_evals": evals,
+            "call_ms": w_ms, "search_kernel_ms": k_ms,
+            "injections_per_s": ninj / (w_ms * 1e-3),
+            "trial_points_per_s": pp / (w_ms * 1e-3),
+            "recovered_frac": float(np.mean(res["recovered"] == 1)),
+            "by_period": frac,
+            "roofline": roofline(pp, evals, k_ms),
+            "cpu_baseline": cpu}
+
+
 def suite(args):
     import paper_1112_1701_amd as bls
     import synth
@@ -737,7 +807,8 @@ def suite(args):
     torch.cuda.set_device(0)
     names = args.workloads.split(",")
     extra = {"window": suite_window, "variability": suite_variability,
-             "unbinned": suite_unbinned, "detect": suite_detect}
+             "unbinned": suite_unbinned, "detect": suite_detect,
+             "recovery": suite_recovery}
     for name in names:
         if name in extra:
             print(json.dumps(extra[name](args, bls)), flush=True)
@@ -764,6 +835,69 @@ def _as_batch(lc):
                        [lc.truth])
 
 
+def probes():
+    """Micro-benchmarks of the rates the search kernel's design rests on
+    (libbls_probes.so): LDS atomics by width and type at random addresses,
+    64-bit LDS reads by lane stride, VALU issue by instruction type.  One JSON
+    line; rates per CU per clock at the device's reported peak clock."""
+    import ctypes
+
+    import torch
+    torch.cuda.set_device(0)
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    clock_hz = 2.4e9
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1112_1701_amd",
+                                   "libbls_probes.so"))
+    for f in (lib.bls_probe_lds_atomic, lib.bls_probe_lds_read,
+              lib.bls_probe_valu):
+        f.restype = ctypes.c_int
+    grid = cus * 8
+    out = {"probe": "gfx950 rates", "cus": cus,
+           "clock_hz_assumed": clock_hz, "grid": grid, "block": 256}
+    ms = ctypes.c_double()
+
+    def per_cu_clk(count, t_ms):
+        return count / (t_ms * 1e-3) / cus / clock_hz
+
+    atom = {}
+    for name, kind in (("ds_add_u64", 0), ("ds_add_u32", 1),
+                       ("ds_add_f32", 2)):
+        for span in (1024, 4096):
+            iters = 4096
+            st = lib.bls_probe_lds_atomic(kind, span, iters, grid,
+                                          ctypes.byref(ms))
+            if st != 0:
+                raise RuntimeError("probe %s failed: %d" % (name, st))
+            n = grid * 256.0 * iters
+            atom["%s_span%d" % (name, span)] = {
+                "ms": ms.value, "per_s": n / (ms.value * 1e-3),
+                "lanes_per_cu_clk": per_cu_clk(n, ms.value)}
+    out["lds_atomics"] = atom
+    rd = {}
+    for stride in (1, 2, 8, 16, 17, 32):
+        iters = 8192
+        st = lib.bls_probe_lds_read(stride, iters, grid, ctypes.byref(ms))
+        if st != 0:
+            raise RuntimeError("probe read failed: %d" % st)
+        n = grid * 256.0 * iters
+        rd["lane_stride_%d" % stride] = {
+            "ms": ms.value, "bytes_per_cu_clk": per_cu_clk(8 * n, ms.value)}
+    out["lds_read_b64"] = rd
+    va = {}
+    for name, kind in (("v_fma_f32", 0), ("v_add_f32", 3), ("v_mul_f64", 1),
+                       ("v_lshl_add_u32", 2)):
+        iters = 16384
+        st = lib.bls_probe_valu(kind, iters, grid, ctypes.byref(ms))
+        if st != 0:
+            raise RuntimeError("probe valu failed: %d" % st)
+        waves = grid * 4.0 * 8 * iters
+        va[name] = {"ms": ms.value,
+                    "wave_instr_per_cu_clk": per_cu_clk(waves, ms.value)}
+    out["valu"] = va
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """Three device copies of 2^28 float32 (1 GiB each), for the counters."""
     import torch
@@ -788,13 +922,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--workloads", default="plain,uniform,uneven,long,"
-                    "serving,window,variability,unbinned,detect")
+                    "serving,window,variability,unbinned,detect,recovery")
     ap.add_argument("--suite-steps", type=int, default=3)
     ap.add_argument("--rates", default="100,500,1000,2000,5000")
     ap.add_argument("--pool", type=int, default=300)
     ap.add_argument("--max-requests", type=int, default=1500)
     ap.add_argument("--seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--probes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the search shards by curve with "
@@ -803,6 +938,8 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+    elif args.probes:
+        probes()
     elif args.suite:
         suite(args)
     else:

@@ -252,12 +252,15 @@ const char *bls_status_string(int status);
  * binned search, ties going to the smaller m, then to the earlier start in
  * phase order.
  * batch: as for bls_search_device (device times, flux, weights, periods);
- * nbins is ignored and qmin/qmax are phase fractions; at most 4096 points
- * per curve.  out: device arrays [results]: FP32 SR and depth, and the
+ * nbins is ignored and qmin/qmax are phase fractions; at most 2^20 points
+ * per curve (curves above 4096 points keep their per-point arrays in a
+ * plan-owned device workspace instead of LDS, about 36 bytes per point per
+ * resident workgroup, at most about 1 GiB, and run slower).  out: device arrays [results]: FP32 SR and depth, and the
  * input indices (within the curve) of the best box's first and last points
  * in phase order (-1 where no box); best_index per curve.  Asynchronous on
  * the plan's stream: bls_synchronize reports invalid data.  Errors:
- * INVALID_ARG, CAPACITY (a curve above 4096 points, plan limits), DEVICE.
+ * INVALID_ARG, CAPACITY (a curve above 2^20 points, plan limits), DEVICE,
+ * NO_MEMORY (the workspace of long curves).
  */
 typedef struct {
     float *sr;
@@ -329,6 +332,64 @@ int bls_detect_device(bls_plan *plan, const bls_batch *batch, const float *sr,
 int bls_eclipse_window_device(bls_plan *plan, const bls_batch *cadences,
                               int32_t nphase, double duration,
                               int32_t min_eclipses, int32_t *observed);
+
+/*
+ * Injection-recovery: the detection efficiency of a cadence through the
+ * search itself (the paper's detection-efficiency simulations on real
+ * cadences, section 5, Discussion and conclusions, with each simulated
+ * eclipse found by the box search and its detection statistic instead of
+ * only counted on the cadence).  Every injection is a copy of one cadence
+ * with its own flux realization and one box eclipse:
+ *   t0 = min kept time (weight > 0; all points if weights is NULL), d = t - t0;
+ *   injection i (period P_i > 0, start phase phi_i in [0, 1), duty cycle q_i
+ *   in (0, 1), finite depth delta_i), in FP64 with this operation order:
+ *   f = 1/P_i, c = d f, u = c - phi_i, v = u - floor(u); a kept point with
+ *   v < q_i gets flux base_i - delta_i, every other point base_i.
+ * Each copy is searched over the shared trial grid (nbins, qmin, qmax) as by
+ * bls_search_device, and its periodogram's detection statistics are taken
+ * as by bls_detect_device (window); the injection is recovered when SDE >=
+ * sde_threshold and the best period P_b (first period of the largest SR)
+ * satisfies |P_b - h P_i| <= ptol h P_i for some h in {1, 1/2, 2}.
+ * The batch is ninj copies of n points: ninj <= max_curves, ninj * n <=
+ * max_points and ninj * nperiods <= max_periods of the plan.
+ */
+typedef struct {
+    int32_t ninj;               /* injections                                */
+    int32_t nbins;              /* phase bins of the search                  */
+    int64_t n;                  /* points of the cadence (>= 2)              */
+    const double *times;        /* DEVICE [n]                                */
+    const double *weights;      /* DEVICE [n] or NULL (unit weights)         */
+    const double *base_flux;    /* DEVICE [ninj * n], injection-major        */
+    const double *inj_period;   /* host [ninj]                               */
+    const double *inj_phase;    /* host [ninj]                               */
+    const double *inj_q;        /* host [ninj]                               */
+    const double *inj_depth;    /* host [ninj]                               */
+    const double *periods;      /* DEVICE [nperiods] trial grid              */
+    int64_t nperiods;
+    double qmin, qmax;          /* box duty-cycle range of the search        */
+    double window;              /* detection: relative suppression window    */
+    double sde_threshold;
+    double ptol;                /* relative period tolerance (>= 0)          */
+} bls_recovery_config;
+
+typedef struct {
+    int32_t *recovered;         /* host [ninj]: 1, 0, or -1 for a copy with
+                                   invalid data or trial periods (required)  */
+    int64_t *best_index;        /* host [ninj] or NULL                       */
+    double *sde;                /* host [ninj] or NULL                       */
+    float *sr;                  /* DEVICE [ninj * nperiods] or NULL: the
+                                   periodograms, injection-major             */
+    double *flux;               /* DEVICE [ninj * n] or NULL: the injected
+                                   fluxes                                    */
+} bls_recovery_results;
+
+/* Synchronous on the plan's stream.  Errors: INVALID_ARG (arguments, an
+ * injection parameter, nbins or q range), CAPACITY (plan limits), DEVICE,
+ * NO_MEMORY.  Copies with invalid data are reported in recovered (-1), not
+ * as an error. */
+int bls_injection_recovery_device(bls_plan *plan,
+                                  const bls_recovery_config *cfg,
+                                  const bls_recovery_results *out);
 
 /*
  * High-variability pre-search (the step before the box search, section
@@ -442,7 +503,9 @@ typedef struct bls_server bls_server;
 typedef struct {
     int32_t device;
     int32_t max_slots;            /* requests resident on the device at once  */
-    int64_t arena_bytes;          /* device bytes for resident requests       */
+    int64_t arena_bytes;          /* device bytes of resident requests at once
+                                     (40 per point, 24 per trial period, any
+                                     mix; twice this much is reserved)        */
     int32_t max_nbins;            /* <= BLS_MAX_NBINS                          */
     int32_t min_in_points;        /* as for a plan                             */
     uint32_t flags;               /* BLS_DIP_ONLY                              */

@@ -30,6 +30,7 @@ from .api import (  # noqa: F401
     bls_eclipse_window_device,
     bls_variability_device,
     bls_search_unbinned_device,
+    bls_injection_recovery_device,
     bls_server_config_init,
     bls_server_create,
     bls_server_submit,

@@ -99,6 +99,22 @@ class BlsVariabilityResults(C.Structure):
                 ("bin_std", C.c_void_p), ("bin_count", C.c_void_p)]
 
 
+class BlsRecoveryConfig(C.Structure):
+    _fields_ = [("ninj", C.c_int32), ("nbins", C.c_int32), ("n", C.c_int64),
+                ("times", C.c_void_p), ("weights", C.c_void_p),
+                ("base_flux", C.c_void_p), ("inj_period", C.c_void_p),
+                ("inj_phase", C.c_void_p), ("inj_q", C.c_void_p),
+                ("inj_depth", C.c_void_p), ("periods", C.c_void_p),
+                ("nperiods", C.c_int64), ("qmin", C.c_double),
+                ("qmax", C.c_double), ("window", C.c_double),
+                ("sde_threshold", C.c_double), ("ptol", C.c_double)]
+
+
+class BlsRecoveryResults(C.Structure):
+    _fields_ = [("recovered", C.c_void_p), ("best_index", C.c_void_p),
+                ("sde", C.c_void_p), ("sr", C.c_void_p), ("flux", C.c_void_p)]
+
+
 class BlsRequest(C.Structure):
     _fields_ = [("times", C.c_void_p), ("flux", C.c_void_p),
                 ("weights", C.c_void_p), ("n", C.c_int64),
@@ -181,6 +197,7 @@ def load():
         "bls_variability_device": (C.c_int, [P, P, P, P]),
         "bls_search_unbinned_device": (C.c_int, [P, P, P]),
         "bls_search_device_noalloc": (C.c_int, [P, P, C.c_uint32, I32, P]),
+        "bls_injection_recovery_device": (C.c_int, [P, P, P]),
     }
     optional = {
         "bls_server_config_init": (None, [P]),

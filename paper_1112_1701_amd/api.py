@@ -247,6 +247,49 @@ def bls_search_device_noalloc(n_off, times, flux, weights, periods, p_off,
         C.c_void_p(stream) if stream else None))
 
 
+def bls_injection_recovery_device(plan, times, weights, base_flux,
+                                  inj_period, inj_phase, inj_q, inj_depth,
+                                  periods, nbins, qmin, qmax, window=0.01,
+                                  sde_threshold=7.0, ptol=0.01, sr=None,
+                                  flux=None):
+    """Injection-recovery of one cadence (synchronous).
+
+    times/weights/periods: torch float64 device tensors ([n], [n] or None,
+    [nperiods]); base_flux: device float64 [ninj, n] (or flat); inj_*: host
+    arrays [ninj].  sr (device float32 [ninj * nperiods]) and flux (device
+    float64 [ninj * n]) optionally receive the periodograms and the injected
+    fluxes.  Returns a dict of numpy arrays: recovered (1, 0, -1 for invalid
+    data), best_index, sde.
+    """
+    n = int(times.shape[0])
+    prm = [_f64(np.broadcast_to(np.asarray(v, np.float64), (len(inj_period),)))
+           for v in (inj_period, inj_phase, inj_q, inj_depth)]
+    ninj = prm[0].shape[0]
+    cfg = L.BlsRecoveryConfig()
+    cfg.ninj, cfg.nbins, cfg.n = ninj, int(nbins), n
+    cfg.times = times.data_ptr()
+    cfg.weights = None if weights is None else weights.data_ptr()
+    cfg.base_flux = base_flux.data_ptr()
+    cfg.inj_period, cfg.inj_phase, cfg.inj_q, cfg.inj_depth = \
+        [v.ctypes.data for v in prm]
+    cfg.periods = periods.data_ptr()
+    cfg.nperiods = int(periods.shape[0])
+    cfg.qmin, cfg.qmax = float(qmin), float(qmax)
+    cfg.window, cfg.sde_threshold, cfg.ptol = (float(window),
+                                               float(sde_threshold),
+                                               float(ptol))
+    rec = np.empty(ninj, np.int32)
+    best = np.empty(ninj, np.int64)
+    sde = np.empty(ninj, np.float64)
+    o = L.BlsRecoveryResults(rec.ctypes.data, best.ctypes.data,
+                             sde.ctypes.data,
+                             None if sr is None else sr.data_ptr(),
+                             None if flux is None else flux.data_ptr())
+    _check(L.load().bls_injection_recovery_device(plan, C.byref(cfg),
+                                                  C.byref(o)), plan)
+    return dict(recovered=rec, best_index=best, sde=sde)
+
+
 def bls_search_unbinned_device(plan, n_off, times, flux, weights, periods,
                                p_off, qmin, qmax, sr, depth, first_point,
                                last_point, best_index):

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbls_mi355x.so")
 
 SOURCES = ["bls_kernels.hip", "bls_plan.cpp", "bls_autotune.cpp",
-           "bls_server.cpp", "bls_noalloc.hip"]
+           "bls_server.cpp", "bls_noalloc.hip", "bls_recovery.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -37,6 +37,24 @@ def _compile(src: str) -> str:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout,
                                                              r.stderr))
     return obj
+
+
+PROBES_SRC = "bls_probes.hip"
+PROBES_LIB = os.path.join(HERE, "libbls_probes.so")
+
+
+def build_probes(verbose: bool = False) -> str:
+    """The micro-benchmark library libbls_probes.so (bench.py --probes)."""
+    obj = _compile(PROBES_SRC)
+    tmp = PROBES_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
+    os.replace(tmp, PROBES_LIB)
+    if verbose:
+        print("built", PROBES_LIB)
+    return PROBES_LIB
 
 
 def build(verbose: bool = False) -> str:
@@ -59,4 +77,5 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_probes(verbose=True)
     sys.exit(0)

@@ -15,6 +15,7 @@ namespace bls {
 
 constexpr int kBlock = 256;        // threads per workgroup
 constexpr int kTileMax = 32;       // largest period tile
+constexpr int kGroupMax = 32;      // largest group of periods per work item
 constexpr int kPPT = 4;            // points held in registers per thread
 constexpr int kQBitsMax = 30;      // fixed-point magnitude bits per point
 constexpr int kMaxParts = 8;       // work partitions (one per XCD)
@@ -61,6 +62,12 @@ struct CurveDesc {
   // complement and for the reported statistic
   double Wtot;          // total weight (the kept count for unit weights)
   double Stot;          // total signal (about 0: the values are centred)
+  // ---- written by the host planner: work items are groups of `group`
+  // consecutive periods (0: one tile), searched `tile` at a time; the first
+  // group of the curve is `galign` periods short, so that later groups start
+  // where the result index is a multiple of `group`
+  int32_t group;
+  int32_t galign;
 };
 
 struct PrepArgs {
@@ -95,6 +102,11 @@ struct SearchArgs {
   unsigned long long *best_key;  // per curve, zeroed before the launch
   int32_t hist_bytes;         // dynamic LDS for histograms
   int32_t ucap;               // unbinned search: largest curve (points)
+  // unbinned search of curves above kUnbinnedMaxPoints: a device workspace
+  // of uws_stride bytes per workgroup holds the per-point arrays (nullptr:
+  // they are in LDS)
+  unsigned char *uws;
+  int64_t uws_stride;
   // Work partitions: items [part_begin[x], part_begin[x+1]) belong to
   // partition x, which workgroups with blockIdx.x % nparts == x drain first
   // (workgroups are dispatched to the XCDs round-robin, so a partition's
@@ -111,11 +123,13 @@ inline void single_partition(SearchArgs &a) {
   for (int x = 0; x <= kMaxParts; ++x) a.part_begin[x] = x == 0 ? 0 : a.nitems;
 }
 
-// Unbinned search: LDS bytes for curves of up to n points.
-int unbinned_lds_bytes(int n, bool weighted);
+// Unbinned search: bytes of per-point arrays for curves of up to n points
+// (LDS, or a workspace slice per workgroup above kUnbinnedMaxPoints).
+int64_t unbinned_lds_bytes(int n, bool weighted);
 int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream);
-int unbinned_blocks_per_cu(bool weighted, bool dip_only, int lds_bytes, int *blocks);
-constexpr int kUnbinnedMaxPoints = 4096;
+int unbinned_blocks_per_cu(bool weighted, bool dip_only, bool glob, int lds_bytes, int *blocks);
+constexpr int kUnbinnedMaxPoints = 4096;         // per-point arrays in LDS
+constexpr int kUnbinnedMaxPointsGlobal = 1 << 20;  // in a device workspace
 
 struct DetectDesc {
   int64_t p_off;     // first trial period of the curve

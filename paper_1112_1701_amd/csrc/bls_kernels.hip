@@ -35,6 +35,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "bls_device.h"
 #include "../../include/bls.h"
@@ -741,44 +742,80 @@ __device__ inline ItemRef claim_item(const SearchArgs &a, unsigned &done_mask, S
 }
 
 // Unit-weight kernels are held to 64 VGPRs (8 waves per SIMD): with tiles of
-// up to 7 periods, 8 workgroups then fit a CU's LDS and registers alike.
-template <bool WEIGHTED, bool DIP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WEIGHTED ? 6 : 8)))
+// up to 7 periods, 8 workgroups then fit a CU's LDS and registers alike, at
+// the price of a few spills in the item set-up.  Where the tile's LDS allows
+// no more than 6 workgroups per CU anyway, the WIDE copy (80 VGPRs, no
+// spills) runs instead; weighted kernels always have 80.
+template <bool WEIGHTED, bool DIP, bool WIDE>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((WEIGHTED || WIDE) ? 6 : 8)))
 void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned long long s_hist[];
   __shared__ double s_f[kTileMax];
   __shared__ unsigned long long s_best[kTileMax];
   __shared__ int s_nonempty[kTileMax];
+  // results of the item's periods, written out together at its end
+  __shared__ float s_rsr[kGroupMax];
+  __shared__ float s_rdp[kGroupMax];
+  __shared__ int s_rjk[kGroupMax];      // j & 0xFFFF | k << 16
+  __shared__ unsigned long long s_gkey;  // the item's largest (SR, ~period)
   __shared__ long long s_item;
   __shared__ int s_curve;
-  __shared__ int s_tile;
+  __shared__ int s_p0, s_gp0, s_gp1, s_t, s_edge;
 
   const int tid = threadIdx.x;
   constexpr int wpb = WEIGHTED ? 2 : 1;
-  // Thread 0 claims each item one step ahead, while the workgroup works on
-  // the current one, so the claim's atomic and lookups are off the path.
+  // A work item is a group of consecutive periods of one curve, searched one
+  // tile of periods per pass of this loop; the tile's results are staged in
+  // LDS and the group's are written out together after its last tile.
+  // Thread 0 claims the next group one step ahead, while the workgroup
+  // works, so the claim's atomic and lookups are off the path.  The group
+  // being searched (its item, curve, periods [gp0, gp1), tile t and the
+  // current tile's start p0) lives in LDS, written and read by thread 0, so
+  // the tile body keeps the register footprint of one tile.
   unsigned done_mask = 0u;
   SegCache sc = {0, 0, 0, 0};
   ItemRef nx = {-1, 0, 0};
-  if (tid == 0) nx = claim_item(a, done_mask, sc);
+  if (tid == 0) {
+    nx = claim_item(a, done_mask, sc);
+    s_p0 = 0;
+    s_t = 0;
+    s_gp1 = 0;
+  }
 
   for (;;) {
     if (tid == 0) {
-      s_item = nx.item;
-      s_curve = nx.curve;
-      s_tile = nx.tile;
+      int p0 = s_p0 + s_t;
+      int edge = 0;
+      if (p0 >= s_gp1) {  // next group (groups are never empty)
+        edge = 1;         // first tile of the group
+        s_item = nx.item;
+        s_curve = nx.curve;
+        if (nx.item >= 0) {
+          const CurveDesc *d = a.curves + nx.curve;
+          const int G = d->group > 0 ? d->group : d->tile;
+          const int gp0 = max(0, nx.tile * G - d->galign);
+          s_t = d->tile;
+          s_gp0 = gp0;
+          s_gp1 = min(d->nperiods, (nx.tile + 1) * G - d->galign);
+          p0 = gp0;
+        }
+      }
+      if (p0 + s_t >= s_gp1) edge |= 2;  // last tile of the group
+      s_p0 = p0;
+      s_edge = edge;
     }
     __syncthreads();
     if (s_item < 0) break;
     // Item values are uniform: keep them (and the curve record) scalar.
     const int c = __builtin_amdgcn_readfirstlane(s_curve);
-    const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+    const int p0 = __builtin_amdgcn_readfirstlane(s_p0);
+    const int edge = __builtin_amdgcn_readfirstlane(s_edge);
     __syncthreads();  // everyone has read the item before thread 0 takes the next
-    if (tid == 0) nx = claim_item(a, done_mask, sc);
+    if (tid == 0 && (edge & 1)) nx = claim_item(a, done_mask, sc);
 
     const CurveDesc cd = a.curves[c];
-    const int p0 = tile * cd.tile;
-    const int np = min(cd.tile, cd.nperiods - p0);
+    const int np = min(cd.tile, __builtin_amdgcn_readfirstlane(s_gp1) - p0);
     // Every item reaches the one barrier at the end of the loop body (no
     // `continue`: a second way into the loop header that skips thread 0's
     // fetch lets the compiler keep the other lanes circling the header
@@ -793,6 +830,7 @@ void search_kernel(SearchArgs a) {
         a.kwidth[r] = -1;
       }
     } else {
+    if (tid == 0 && (edge & 1)) s_gkey = 0ull;
     const int nb = cd.nbins;
     const int kmin = cd.kmin;
     const int kmax = cd.kmax;
@@ -953,14 +991,13 @@ void search_kernel(SearchArgs a) {
     if (tid < np) {
       const int t = tid;
       const int p = p0 + t;
-      const int64_t r = cd.r_off + p;
+      const int g = p - s_gp0;  // staging slot
       const unsigned long long key = s_best[t];
       float srf = 0.0f;
       if (key == 0ull) {
-        a.sr[r] = 0.0f;
-        a.depth[r] = NAN;
-        a.jstart[r] = -1;
-        a.kwidth[r] = -1;
+        s_rsr[g] = 0.0f;
+        s_rdp[g] = NAN;
+        s_rjk[g] = -1;
       } else {
         const unsigned idx = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
         const int k = (int)(idx / (unsigned)nb);
@@ -984,24 +1021,33 @@ void search_kernel(SearchArgs a) {
         const double sr = sqrt(S * S / den) * cd.out_scale;
         const double depth = -S * W / den * cd.out_scale;
         srf = (float)sr;
-        a.sr[r] = srf;
-        a.depth[r] = (float)depth;
-        a.jstart[r] = j;
-        a.kwidth[r] = k;
+        s_rsr[g] = srf;
+        s_rdp[g] = (float)depth;
+        s_rjk[g] = (j & 0xFFFF) | (k << 16);
       }
-      s_best[t] = ((unsigned long long)__float_as_uint(srf) << 32) |
-                  (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+      __hip_atomic_fetch_max(&s_gkey,
+                             ((unsigned long long)__float_as_uint(srf) << 32) |
+                                 (unsigned long long)(0xFFFFFFFFu - (unsigned)p),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    __syncthreads();
-    // One global update per item: the tile's largest (SR, ~period) key.
-    if (tid < 64) {
-      unsigned long long ck = tid < np ? s_best[tid] : 0ull;
-      for (int o = 16; o > 0; o >>= 1) {
-        const unsigned long long other = __shfl_xor(ck, o, 64);
-        ck = other > ck ? other : ck;
+    // After the group's last tile: its results, consecutive periods of the
+    // curve, written out together (whole result lines where groups are
+    // line-aligned), and one global update of the curve's best key.
+    if (edge & 2) {
+      __syncthreads();
+      const int gp0 = s_gp0;
+      const int ng = s_gp1 - gp0;
+      for (int t = tid; t < ng; t += kBlock) {
+        const int64_t r = cd.r_off + gp0 + t;
+        const int jk = s_rjk[t];
+        a.sr[r] = s_rsr[t];
+        a.depth[r] = s_rdp[t];
+        a.jstart[r] = (int)(short)(jk & 0xFFFF);
+        a.kwidth[r] = jk >> 16;
       }
       if (tid == 0)
-        __hip_atomic_fetch_max(a.best_key + c, ck, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(a.best_key + c, s_gkey, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
     }  // valid item
     __syncthreads();
@@ -1791,9 +1837,12 @@ __device__ inline double fwd_phase(double pi, double pj, int i, int j) {
   return j > i ? pj - pi : (pj + 1.0) - pi;
 }
 
-template <bool WEIGHTED, bool DIP>
+// GLOB: the per-point arrays live in the workgroup's slice of a device
+// workspace instead of LDS (curves longer than LDS holds); the steps are the
+// same, only slower.
+template <bool WEIGHTED, bool DIP, bool GLOB>
 __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
-  extern __shared__ __align__(16) unsigned char s_raw[];
+  extern __shared__ __align__(16) unsigned char s_lds[];
   __shared__ long long s_item;
   __shared__ int s_curve;
   __shared__ int s_per;
@@ -1807,6 +1856,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   const int tid = threadIdx.x;
   const int N = a.ucap;
   const int Mc = pow2_at_least(N);
+  unsigned char *s_raw = GLOB ? a.uws + (int64_t)blockIdx.x * a.uws_stride : s_lds;
   double *ph_u = reinterpret_cast<double *>(s_raw);
   double *sph = ph_u + N;
   int *sq = reinterpret_cast<int *>(sph + N);
@@ -1940,8 +1990,8 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     // Runs from every start position, four run steps per iteration with
     // their values loaded together, up to the longest run a box shorter than
     // qhi in phase can hold.  S and R are summed in FP64, which is
-    // exact here (|q|, w < 2^30 and at most kUnbinnedMaxPoints points keep
-    // every partial sum below 2^53).  Each step is screened against theta,
+    // exact here (|q|, w < 2^qbits with qbits <= 63 - 2 bitlen(n) keep
+    // every partial sum below 2^53 at any curve length).  Each step is screened against theta,
     // the best value any lane of the workgroup has found so far in this
     // period (s_theta, raised as lanes improve; the lanes' final bests go to
     // s_vbits as before): a run with
@@ -2064,14 +2114,18 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   }
 }
 
-template <bool W, bool D>
+template <bool W, bool D, bool G>
 const void *unbinned_fn() {
-  return reinterpret_cast<const void *>(&unbinned_kernel<W, D>);
+  return reinterpret_cast<const void *>(&unbinned_kernel<W, D, G>);
 }
 
-const void *pick_unbinned(bool weighted, bool dip) {
-  if (weighted) return dip ? unbinned_fn<true, true>() : unbinned_fn<true, false>();
-  return dip ? unbinned_fn<false, true>() : unbinned_fn<false, false>();
+const void *pick_unbinned(bool weighted, bool dip, bool glob) {
+  if (glob) {
+    if (weighted) return dip ? unbinned_fn<true, true, true>() : unbinned_fn<true, false, true>();
+    return dip ? unbinned_fn<false, true, true>() : unbinned_fn<false, false, true>();
+  }
+  if (weighted) return dip ? unbinned_fn<true, true, false>() : unbinned_fn<true, false, false>();
+  return dip ? unbinned_fn<false, true, false>() : unbinned_fn<false, false, false>();
 }
 
 __global__ void fill_kernel(unsigned long long *counter, unsigned long long *keys, int32_t nkeys) {
@@ -2088,14 +2142,35 @@ __global__ void best_index_kernel(unsigned long long *keys, int32_t n) {
   }
 }
 
-template <bool W, bool D>
+template <bool W, bool D, bool WIDE = false>
 const void *search_fn() {
-  return reinterpret_cast<const void *>(&search_kernel<W, D>);
+  return reinterpret_cast<const void *>(&search_kernel<W, D, WIDE>);
 }
 
-const void *pick(bool weighted, bool dip) {
+const void *pick_narrow(bool weighted, bool dip) {
   if (weighted) return dip ? search_fn<true, true>() : search_fn<true, false>();
   return dip ? search_fn<false, true>() : search_fn<false, false>();
+}
+
+// The unit-weight kernel copy for a tile of hist_bytes of LDS: the 64-VGPR
+// copy where its LDS lets more than 6 workgroups share a CU, the 80-VGPR one
+// otherwise (BLS_WIDE_REGS=0/1 forces the choice).
+const void *pick(bool weighted, bool dip, int hist_bytes) {
+  if (weighted) return pick_narrow(true, dip);
+  int wide = -1;
+  if (const char *e = getenv("BLS_WIDE_REGS")) wide = atoi(e) != 0 ? 1 : 0;
+  if (wide < 0) {
+    const void *fn = pick_narrow(false, dip);
+    int blocks = 0;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, hist_bytes) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, (size_t)hist_bytes) !=
+            hipSuccess)
+      return fn;
+    wide = blocks <= 6 ? 1 : 0;
+  }
+  if (!wide) return pick_narrow(false, dip);
+  return dip ? search_fn<false, true, true>() : search_fn<false, false, true>();
 }
 
 }  // namespace
@@ -2116,7 +2191,7 @@ int launch_prep(const PrepArgs &a, void *stream) {
 
 int launch_search(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream) {
   if (a.nitems <= 0) return 0;
-  const void *fn = pick(weighted, dip_only);
+  const void *fn = pick(weighted, dip_only, a.hist_bytes);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, a.hist_bytes);
   if (e != hipSuccess) return (int)e;
   void *args[] = {const_cast<SearchArgs *>(&a)};
@@ -2180,15 +2255,15 @@ int window_blocks_per_cu(int lds_bytes, int *blocks) {
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
 }
 
-int unbinned_lds_bytes(int n, bool weighted) {
-  const int N = n < 1 ? 1 : n;
-  const int M = pow2_at_least(N);
+int64_t unbinned_lds_bytes(int n, bool weighted) {
+  const int64_t N = n < 1 ? 1 : n;
+  const int64_t M = pow2_at_least((int)N);
   return 8 * N + 8 * N + 4 * N + 4 * N + 4 * N + 4 * (M + 1) + (weighted ? 4 * N : 0);
 }
 
 int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream) {
   if (a.nitems <= 0) return 0;
-  const void *fn = pick_unbinned(weighted, dip_only);
+  const void *fn = pick_unbinned(weighted, dip_only, a.uws != nullptr);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, a.hist_bytes);
   if (e != hipSuccess) return (int)e;
   void *args[] = {const_cast<SearchArgs *>(&a)};
@@ -2198,15 +2273,16 @@ int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid,
   return (int)hipGetLastError();
 }
 
-int unbinned_blocks_per_cu(bool weighted, bool dip_only, int lds_bytes, int *blocks) {
-  const void *fn = pick_unbinned(weighted, dip_only);
+int unbinned_blocks_per_cu(bool weighted, bool dip_only, bool glob, int lds_bytes,
+                           int *blocks) {
+  const void *fn = pick_unbinned(weighted, dip_only, glob);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return (int)e;
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
 }
 
 int search_blocks_per_cu(bool weighted, bool dip_only, int hist_bytes, int *blocks) {
-  const void *fn = pick(weighted, dip_only);
+  const void *fn = pick(weighted, dip_only, hist_bytes);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, hist_bytes);
   if (e != hipSuccess) return (int)e;
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)hist_bytes);

@@ -288,9 +288,9 @@ int validate_batch_into(const bls_plan_config &cfg, const bls_batch &b, bool che
         err = msg;
         return BLS_ERR_INVALID_ARG;
       }
-      if (s.n > kUnbinnedMaxPoints) {
+      if (s.n > kUnbinnedMaxPointsGlobal) {
         snprintf(msg, sizeof msg, "curve %d has %lld points (the unbinned search takes at most %d)",
-                 c, (long long)s.n, kUnbinnedMaxPoints);
+                 c, (long long)s.n, kUnbinnedMaxPointsGlobal);
         err = msg;
         return BLS_ERR_CAPACITY;
       }
@@ -420,6 +420,18 @@ void layout_partitions(bls_plan *p, const std::vector<double> &cost,
   out.nitems = items;
 }
 
+int item_group(const bls_plan *p, const std::vector<CurveShape> &shapes) {
+  if (const char *e = getenv("BLS_ITEM_GROUP")) {
+    const int g = atoi(e);  // 0: one tile per item; kGroupMax: groups
+    return g == kGroupMax ? kGroupMax : 0;
+  }
+  int64_t periods = 0;
+  for (const CurveShape &s : shapes) periods += s.nperiods;
+  // at least four groups per workgroup of a full grid (eight per CU)
+  const int64_t want = (int64_t)kGroupMax * 4 * 8 * std::max(p->num_cus, 1);
+  return periods >= want ? kGroupMax : 0;
+}
+
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out) {
   const int nc = (int)shapes.size();
@@ -431,6 +443,10 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
   out.ncurves = nc;
   out.weighted = weighted;
 
+  // Work items: groups of kGroupMax consecutive periods, aligned to whole
+  // result lines and written out together, when the batch has enough of
+  // them for several items per resident workgroup; one tile each otherwise.
+  const int G = item_group(p, shapes);
   // Per-curve tile: as many periods as fit the LDS budget, at least one.
   int hist_bytes = 0;
   std::vector<double> item_cost(nc);
@@ -440,9 +456,13 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
     // each distinct period range is checked once (a shared grid by curve 0)
     fill_curve_desc(s, weighted, tc, c == 0 || s.p_off != shapes[0].p_off, true, d);
     const int T = d.tile;
+    if (G > 0) {
+      d.group = G;
+      d.galign = (int32_t)(s.r_off % G);
+    }
     hist_bytes = std::max(hist_bytes, T * d.hstride * 8 * wpb);
     const double nw = (double)(s.kmax - s.kmin + 1);
-    item_cost[c] = (double)T * ((double)s.n + 1.6 * (double)s.nbins * nw);
+    item_cost[c] = (double)(G > 0 ? G : T) * ((double)s.n + 1.6 * (double)s.nbins * nw);
     out.total_points += s.n;
     out.total_results += s.nperiods;
     out.trial_points += (double)s.n * (double)s.nperiods;
@@ -459,7 +479,8 @@ int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted
   std::vector<int64_t> items_of(nc);
   for (int c = 0; c < nc; ++c) {
     const CurveDesc &d = p->h_curves[c];
-    items_of[c] = (d.nperiods + d.tile - 1) / d.tile;
+    items_of[c] = d.group > 0 ? ((int64_t)d.nperiods + d.galign + d.group - 1) / d.group
+                              : (d.nperiods + d.tile - 1) / d.tile;
   }
   layout_partitions(p, item_cost, items_of, out);
   const int64_t items = out.nitems;
@@ -564,6 +585,8 @@ int enqueue_kernel(bls_plan *p, const PlannedBatch &pb, const double *periods, f
   sa.best_key = reinterpret_cast<unsigned long long *>(best);
   sa.hist_bytes = pb.hist_bytes;
   sa.ucap = pb.ucap;
+  sa.uws = pb.uws;
+  sa.uws_stride = pb.uws_stride;
   sa.nparts = pb.nparts;
   sa.pad_parts = 0;
   for (int x = 0; x <= kMaxParts; ++x) sa.part_begin[x] = pb.part_begin[x];
@@ -605,14 +628,6 @@ TileChoice default_tiles(bool weighted) {
   return tc;
 }
 
-}  // namespace bls
-
-using namespace bls;
-
-namespace {
-
-// Duration of the most recent bracketed kernel launch (the stream must have
-// reached its end event); 0 if there is none.
 double last_kernel_ms(bls_plan *p) {
   if (p->k_recorded == 0) return 0.0;
   const int slot = (int)((p->k_recorded - 1) % bls_plan::kTimeRing);
@@ -677,6 +692,81 @@ int check_device_status(bls_plan *p, int ncurves) {
   return BLS_OK;
 }
 
+
+// Per-curve validity flags of the last prep (1 where the curve's data or
+// trial periods were invalid), read back from the device descriptors.
+int device_status_flags(bls_plan *p, int ncurves, int32_t *bad) {
+  std::vector<CurveDesc> cds(ncurves);
+  hipError_t e = hipMemcpy(cds.data(), p->d_curves, sizeof(CurveDesc) * ncurves,
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(p, e, "read curve status");
+  for (int c = 0; c < ncurves; ++c) bad[c] = cds[c].status != kCurveOk ? 1 : 0;
+  return BLS_OK;
+}
+
+int ensure_detect_buffers(bls_plan *p) {
+  if (p->d_detect_desc) return BLS_OK;
+  hipError_t e;
+  if ((e = device_alloc((void **)&p->d_detect_desc, sizeof(DetectDesc) * p->cfg.max_curves)) ||
+      (e = device_alloc((void **)&p->d_detect_out, sizeof(bls_detection) * p->cfg.max_curves))) {
+    if (p->d_detect_desc) (void)hipFree(p->d_detect_desc);
+    p->d_detect_desc = nullptr;
+    p->d_detect_out = nullptr;
+    return hip_error(p, e, "allocate detection buffers");
+  }
+  return BLS_OK;
+}
+
+int enqueue_detect_shared(bls_plan *p, int ncurves, const double *periods, int64_t nperiods,
+                          const float *sr, int max_peaks, double window, double threshold) {
+  int st = ensure_detect_buffers(p);
+  if (st != BLS_OK) return st;
+  std::vector<DetectDesc> dd(ncurves);
+  for (int c = 0; c < ncurves; ++c) {
+    dd[c].p_off = 0;
+    dd[c].r_off = (int64_t)c * nperiods;
+    dd[c].nperiods = nperiods;
+  }
+  hipStream_t s = p->stream;
+  // a synchronous upload: dd lives on this function's stack
+  hipError_t e = hipMemcpyAsync(p->d_detect_desc, dd.data(), sizeof(DetectDesc) * ncurves,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(p, e, "upload detection descriptors");
+  DetectArgs a;
+  a.desc = p->d_detect_desc;
+  a.periods = periods;
+  a.sr = sr;
+  a.out = p->d_detect_out;
+  a.ncurves = ncurves;
+  a.max_peaks = max_peaks;
+  a.window = window;
+  a.threshold = threshold;
+  if ((e = (hipError_t)launch_detect(a, s)) != hipSuccess) return hip_error(p, e, "launch detection");
+  return BLS_OK;
+}
+
+int ensure_recovery_buffers(bls_plan *p) {
+  if (p->d_inj) return BLS_OK;
+  hipError_t e;
+  if ((e = device_alloc((void **)&p->d_inj, 32 * (size_t)p->cfg.max_curves)) ||
+      (e = device_alloc((void **)&p->d_inj_t0, sizeof(double)))) {
+    if (p->d_inj) (void)hipFree(p->d_inj);
+    p->d_inj = nullptr;
+    p->d_inj_t0 = nullptr;
+    return hip_error(p, e, "allocate injection buffers");
+  }
+  return BLS_OK;
+}
+
+}  // namespace bls
+
+using namespace bls;
+
+namespace {
+
+// Duration of the most recent bracketed kernel launch (the stream must have
+// reached its end event); 0 if there is none.
 // Host-array search of a validated batch (shared by bls_search and
 // bls_search_batch).
 int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &shapes,
@@ -920,7 +1010,8 @@ int bls_plan_destroy(bls_plan *p) {
   drop_graph(p);
   for (void *d : {(void *)p->d_detect_desc, (void *)p->d_detect_out,
                   (void *)p->d_window_desc, (void *)p->d_window_flag,
-                  (void *)p->d_var_noff, (void *)p->d_var_alive, (void *)p->d_var_chip})
+                  (void *)p->d_var_noff, (void *)p->d_var_alive, (void *)p->d_var_chip,
+                  (void *)p->d_uws})
     free_dev(d);
   for (void *d : {(void *)p->d_curves, (void *)p->d_seg_start, (void *)p->d_seg_curve,
                   (void *)p->d_seg_tile0, (void *)p->d_dt, (void *)p->d_q, (void *)p->d_qw,
@@ -1092,15 +1183,38 @@ int bls_search_unbinned_device(bls_plan *p, const bls_batch *b, const bls_unbinn
   layout_partitions(p, cost, items_of, pb);
   const int64_t items = pb.nitems;
   pb.ucap = ucap;
-  pb.hist_bytes = unbinned_lds_bytes(ucap, weighted);
+  // Curves up to kUnbinnedMaxPoints keep their per-point arrays in LDS;
+  // longer ones in a device workspace slice per workgroup.
+  const bool glob = ucap > kUnbinnedMaxPoints;
+  const int64_t arrays = unbinned_lds_bytes(ucap, weighted);
+  pb.hist_bytes = glob ? 0 : (int32_t)arrays;
   if (pb.hist_bytes > p->max_lds - 2048)
     return set_error(p, BLS_ERR_CAPACITY, "curve too long for the unbinned search's LDS");
   int per_cu = 0;
-  if ((e = (hipError_t)unbinned_blocks_per_cu(weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0,
+  if ((e = (hipError_t)unbinned_blocks_per_cu(weighted, (p->cfg.flags & BLS_DIP_ONLY) != 0, glob,
                                               pb.hist_bytes, &per_cu)) != hipSuccess)
     return hip_error(p, e, "occupancy query");
   if (per_cu < 1) return set_error(p, BLS_ERR_CAPACITY, "unbinned kernel does not fit a CU");
-  pb.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)p->num_cus * per_cu));
+  int64_t grid = std::min<int64_t>(items, (int64_t)p->num_cus * per_cu);
+  if (glob) {
+    // at most about 1 GiB of workspace (at least 32 workgroups)
+    const int64_t stride = (arrays + 255) & ~(int64_t)255;
+    grid = std::min<int64_t>(grid, std::max<int64_t>(32, ((int64_t)1 << 30) / stride));
+    const int64_t need = grid * stride;
+    if (need > p->uws_bytes) {
+      // queued unbinned searches may still use the old workspace
+      if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_error(p, e, "synchronize");
+      free_dev(p->d_uws);
+      p->d_uws = nullptr;
+      p->uws_bytes = 0;
+      if ((e = device_alloc((void **)&p->d_uws, (size_t)need)) != hipSuccess)
+        return hip_error(p, e, "allocate unbinned workspace");
+      p->uws_bytes = need;
+    }
+    pb.uws = p->d_uws;
+    pb.uws_stride = stride;
+  }
+  pb.grid = (int32_t)std::max<int64_t>(1, grid);
   p->last = pb;
   if ((e = hipEventRecord(p->ev_begin, p->stream)) != hipSuccess) return hip_error(p, e, "event");
   st = enqueue_search(p, pb, b->times, b->flux, b->weights, b->periods, o->sr, o->depth,
@@ -1131,15 +1245,8 @@ int bls_detect_device(bls_plan *p, const bls_batch *b, const float *sr, int32_t 
     dd[c].r_off = shapes[c].r_off;
     dd[c].nperiods = shapes[c].nperiods;
   }
-  if (!p->d_detect_desc) {
-    if ((e = device_alloc((void **)&p->d_detect_desc, sizeof(DetectDesc) * p->cfg.max_curves)) ||
-        (e = device_alloc((void **)&p->d_detect_out, sizeof(bls_detection) * p->cfg.max_curves))) {
-      if (p->d_detect_desc) (void)hipFree(p->d_detect_desc);
-      p->d_detect_desc = nullptr;
-      p->d_detect_out = nullptr;
-      return hip_error(p, e, "allocate detection buffers");
-    }
-  }
+  st = ensure_detect_buffers(p);
+  if (st != BLS_OK) return st;
   hipStream_t s = p->stream;
   if ((e = hipMemcpyAsync(p->d_detect_desc, dd.data(), sizeof(DetectDesc) * nc,
                           hipMemcpyHostToDevice, s)))

@@ -33,6 +33,8 @@ struct PlannedBatch {
   double trial_points = 0.0;
   double box_evals = 0.0;
   int32_t ucap = 0;         // unbinned search: largest curve (points)
+  unsigned char *uws = nullptr;  // unbinned search: workspace of long curves
+  int64_t uws_stride = 0;        // its bytes per workgroup
   int32_t nparts = 1;       // work partitions (XCDs)
   int64_t part_begin[bls::kMaxParts + 1] = {};
 };
@@ -73,6 +75,15 @@ struct bls_plan {
   // detection buffers (allocated on first use)
   bls::DetectDesc *d_detect_desc = nullptr;
   void *d_detect_out = nullptr;
+
+  // injection-recovery buffers (allocated on first use): per-injection
+  // parameters [max_curves] and the cadence's t0
+  void *d_inj = nullptr;
+  double *d_inj_t0 = nullptr;
+
+  // unbinned search of long curves: per-workgroup workspace (grown as needed)
+  unsigned char *d_uws = nullptr;
+  int64_t uws_bytes = 0;
 
   // eclipse-window buffers (allocated on first use)
   bls::WindowDesc *d_window_desc = nullptr;
@@ -151,6 +162,12 @@ void fill_curve_desc(const CurveShape &s, bool weighted, const TileChoice &tc,
 void layout_partitions(bls_plan *p, const std::vector<double> &cost,
                        const std::vector<int64_t> &items_of, PlannedBatch &out);
 
+// Periods per work item of a batch: kGroupMax when the batch has at least
+// four such groups per workgroup of a full grid (the kernel then writes each
+// item's results as whole lines), else 0 (one period tile per item).  The
+// environment variable BLS_ITEM_GROUP (0 or kGroupMax) overrides the choice.
+int item_group(const bls_plan *p, const std::vector<CurveShape> &shapes);
+
 // Fill the pinned descriptors for a validated batch and size the launch.
 int plan_batch(bls_plan *p, const std::vector<CurveShape> &shapes, bool weighted,
                const TileChoice &tc, PlannedBatch &out);
@@ -184,6 +201,26 @@ int set_error(bls_plan *p, int status, const std::string &msg);
 int set_error_noplan(int status, const char *msg);
 int hip_error(bls_plan *p, hipError_t e, const char *what);
 int width_range(int32_t nbins, double qmin, double qmax, int32_t *kmin, int32_t *kmax);
+
+// Search-kernel duration of the last bracketed launch (ms; 0 if none).
+double last_kernel_ms(bls_plan *p);
+// Call statistics of a planned batch.
+void fill_stats(bls_plan *p, const PlannedBatch &pb, bool replayed);
+// Device buffers of the host-array calls (max_points, max_periods,
+// max_curves sized), allocated on first use.
+int ensure_staging(bls_plan *p);
+// INVALID_ARG naming the first curve whose prep found invalid data.
+int check_device_status(bls_plan *p, int ncurves);
+// Per-curve flags (1: invalid data or trial periods) of the last prep.
+int device_status_flags(bls_plan *p, int ncurves, int32_t *bad);
+// Detection buffers (max_curves descriptors and results), on first use.
+int ensure_detect_buffers(bls_plan *p);
+// Queue the detection kernel over ncurves periodograms of one shared grid,
+// curve c's SR at sr[c * nperiods]; results in p->d_detect_out.
+int enqueue_detect_shared(bls_plan *p, int ncurves, const double *periods, int64_t nperiods,
+                          const float *sr, int max_peaks, double window, double threshold);
+// Injection-recovery buffers, on first use.
+int ensure_recovery_buffers(bls_plan *p);
 
 // Device allocation with the optional failure-injection hook.
 hipError_t device_alloc(void **ptr, size_t bytes);

@@ -22,7 +22,8 @@ namespace bls {
 namespace {
 
 constexpr int kTickBuffers = 2;          // launches in flight
-constexpr int64_t kPeriodsPerPoint = 12; // arena split: period slots per point slot
+constexpr int64_t kBytesPerPoint = 40;   // t, x, w, dt (8 B), q, qw (4 B)
+constexpr int64_t kBytesPerPeriod = 24;  // periods (8 B), sr, depth, jstart, kwidth (4 B)
 constexpr size_t kArenaAlign = 64;       // elements
 
 thread_local std::string g_server_create_error;
@@ -56,6 +57,12 @@ struct Tick {
   std::vector<TickSegment> segs;
 };
 
+// Device bytes a request holds while resident (arena elements, aligned).
+int64_t request_bytes(int64_t n, int64_t np) {
+  const int64_t a = (int64_t)kArenaAlign;
+  return ((n + a - 1) / a * a) * kBytesPerPoint + ((np + a - 1) / a * a) * kBytesPerPeriod;
+}
+
 int cbits_of(int64_t n) {
   int b = 0;
   while (b < 63 && (int64_t(1) << b) <= n) ++b;
@@ -75,6 +82,8 @@ struct bls_server {
   hipStream_t stream = nullptr, copy_stream = nullptr;
 
   int64_t cap_pts = 0, cap_per = 0;
+  int64_t arena_budget = 0;   // bytes of resident requests allowed at once
+  int64_t bytes_peak = 0;     // largest bytes held at once (both regions)
   double *d_t = nullptr, *d_x = nullptr, *d_w = nullptr, *d_dt = nullptr, *d_per = nullptr;
   int32_t *d_q = nullptr, *d_qw = nullptr, *d_js = nullptr, *d_ks = nullptr;
   float *d_sr = nullptr, *d_depth = nullptr;
@@ -236,6 +245,8 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
   a.best_key = s->d_keys;
   a.hist_bytes = hist_bytes;
   a.ucap = 0;
+  a.uws = nullptr;
+  a.uws_stride = 0;
   single_partition(a);
   const bool dip = (s->cfg.flags & BLS_DIP_ONLY) != 0;
   int per_cu = 1;
@@ -347,6 +358,9 @@ void scheduler(bls_server *s) {
           break;
         }
       if (slot < 0) break;
+      const int64_t held = (int64_t)(s->pts_arena.in_use() * kBytesPerPoint +
+                                     s->per_arena.in_use() * kBytesPerPeriod);
+      if (held + request_bytes(r->n, r->np) > s->arena_budget) break;
       const size_t po = s->pts_arena.alloc((size_t)r->n);
       if (po == Arena::kFail) break;
       const size_t pr = s->per_arena.alloc((size_t)r->np);
@@ -354,6 +368,9 @@ void scheduler(bls_server *s) {
         s->pts_arena.release(po);
         break;
       }
+      s->bytes_peak = std::max(s->bytes_peak,
+                               (int64_t)(s->pts_arena.in_use() * kBytesPerPoint +
+                                         s->per_arena.in_use() * kBytesPerPeriod));
       r->slot = slot;
       r->pt_off = po;
       r->pr_off = pr;
@@ -487,11 +504,13 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
       (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)))
     return fail(srv_hip(s, e, "create streams"));
 
-  // Arena: point arrays (t, x, w, dt: 8 B; q, qw: 4 B) and period arrays
-  // (periods 8 B; sr, depth, jstart, kwidth 4 B) in a fixed ratio.
-  const int64_t per_unit = 40 + 24 * kPeriodsPerPoint;
-  s->cap_pts = cfg.arena_bytes / per_unit;
-  s->cap_per = s->cap_pts * kPeriodsPerPoint;
+  // Arena: point arrays and period arrays in two address ranges, each able
+  // to take the whole byte budget, so that any mix of request shapes fits;
+  // admission counts the bytes both ranges hold against the budget (the
+  // reservation is twice arena_bytes).
+  s->arena_budget = cfg.arena_bytes;
+  s->cap_pts = cfg.arena_bytes / kBytesPerPoint;
+  s->cap_per = cfg.arena_bytes / kBytesPerPeriod;
   const size_t P = (size_t)s->cap_pts, Q = (size_t)s->cap_per, M = (size_t)cfg.max_slots;
   struct {
     void **ptr;
@@ -639,8 +658,8 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
   int reject = BLS_OK;
   if (s->device_error)
     reject = srv_error(s, BLS_ERR_DEVICE, "server stopped after a device error");
-  else if (!s->pts_arena.fits_ever((size_t)r->n) || !s->per_arena.fits_ever((size_t)r->np) ||
-           per_period > s->max_lds - 1024)
+  else if (request_bytes(r->n, r->np) > s->arena_budget || !s->pts_arena.fits_ever((size_t)r->n) ||
+           !s->per_arena.fits_ever((size_t)r->np) || per_period > s->max_lds - 1024)
     reject = srv_error(s, BLS_ERR_CAPACITY, "request larger than the server's device arena");
   if (reject != BLS_OK) {
     if (r->pin_off != Arena::kFail) s->pool_arena.release(r->pin_off);
@@ -729,8 +748,8 @@ int bls_server_get_stats(bls_server *s, bls_server_stats *out) {
   out->wall_s =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t_reset).count();
   out->device_bytes_in_use =
-      (int64_t)(s->pts_arena.in_use() * 40 + s->per_arena.in_use() * 24);
-  out->device_bytes_peak = (int64_t)(s->pts_arena.peak() * 40 + s->per_arena.peak() * 24);
+      (int64_t)(s->pts_arena.in_use() * kBytesPerPoint + s->per_arena.in_use() * kBytesPerPeriod);
+  out->device_bytes_peak = s->bytes_peak;
   return BLS_OK;
 }
 

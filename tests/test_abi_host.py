@@ -48,7 +48,9 @@ def test_struct_layouts_match_c():
                "bls_detection": L.BlsDetection,
                "bls_variability_config": L.BlsVariabilityConfig,
                "bls_variability_results": L.BlsVariabilityResults,
-               "bls_unbinned_results": L.BlsUnbinnedResults}
+               "bls_unbinned_results": L.BlsUnbinnedResults,
+               "bls_recovery_config": L.BlsRecoveryConfig,
+               "bls_recovery_results": L.BlsRecoveryResults}
     text = open(HEADER).read()
     for opt, cls in (("bls_request", L.BlsRequest),
                      ("bls_result", L.BlsResult),

@@ -263,3 +263,38 @@ def test_debug_fail_alloc_hook(bls, monkeypatch):
                            lc.qmin, lc.qmax)
     check_curve(lc, g, _orc(lc), label="after failed allocation")
     assert "BLS_DEBUG_FAIL_ALLOC" not in os.environ
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_grouped_items_equal_tile_items(bls, monkeypatch, weighted):
+    """Work items of 32 consecutive periods (results staged in LDS and written
+    as whole lines, groups aligned to the result index) give the same results
+    bit for bit as one tile per item, on curves whose result offsets are not
+    multiples of 32 and whose period counts are not either; and the oracle's."""
+    b = synth.uneven_batch(9, 81 + weighted, n_range=(150, 4000),
+                           np_range=(37, 700), nbins_range=(64, 400),
+                           weighted=weighted)
+    assert any(int(o) % 32 for o in b.p_off[1:-1])
+    got = {}
+    for g in ("0", "32"):
+        monkeypatch.setenv("BLS_ITEM_GROUP", g)
+        ins, outs = _device_batch(b)
+        _say("grouped items", g, "weighted" if weighted else "unit")
+        with bls.Plan(max_curves=b.ncurves, max_points=b.total_points(),
+                      max_periods=int(b.p_off[-1]),
+                      flags=bls.BLS_NO_GRAPH | bls.BLS_NO_AUTOTUNE) as p:
+            _call(bls, p.handle, b, ins, outs)
+            bls.bls_synchronize(p.handle)
+            st = bls.bls_last_stats(p.handle)
+        got[g] = ([o.cpu().numpy() for o in outs], st["work_items"])
+    (a, na), (c, nc) = got["0"], got["32"]
+    assert nc < na
+    for name, x, y in zip(("sr", "depth", "jstart", "kwidth", "best"), a, c):
+        assert np.array_equal(x, y, equal_nan=True), name
+    sr, dp, js, ks, bi = c
+    for k in (0, 4, 8):
+        lc = b.curve(k)
+        lo, hi = int(b.p_off[k]), int(b.p_off[k + 1])
+        check_curve(lc, dict(sr=sr[lo:hi], depth=dp[lo:hi], jstart=js[lo:hi],
+                             kwidth=ks[lo:hi], best_index=bi[k]), _orc(lc),
+                    label="grouped %d" % k)

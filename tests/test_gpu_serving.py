@@ -76,13 +76,46 @@ def test_mix_equals_alone_and_oracle(bls):
                 check_curve(lc, r, o, label="served %d" % k)
 
 
-def test_small_arena_queues_instead_of_failing(bls):
-    reqs = _requests(10, 5252, n_range=(3000, 6000), np_range=(2000, 4000))
-    # one request needs at most ~6000 points; the arena holds about two
-    need = max(lc.n for lc in reqs)
-    arena = int(need * (40 + 24 * 12) * 2.2)
-    _say("small arena", arena)
+def _bytes(lc):
+    up = lambda v: -(-v // 64) * 64
+    return 40 * up(lc.n) + 24 * up(lc.periods.size)
+
+
+def test_arena_takes_any_mix_of_shapes(bls):
+    """Point-heavy and period-heavy requests share one byte budget: requests
+    of 20000 points and 300 periods, then of 600 points and 30000 periods,
+    each kind fitting only because neither region has a fixed share."""
+    heavy_pts = [synth.small_curve(60 + k, 20000, nperiods=300, nbins=200,
+                                   qmin=0.01, qmax=0.1) for k in range(4)]
+    heavy_per = [synth.small_curve(70 + k, 600, nperiods=30000, nbins=200,
+                                   qmin=0.01, qmax=0.1) for k in range(4)]
+    arena = int(2.5 * max(_bytes(lc) for lc in heavy_pts + heavy_per))
+    _say("arena mix", arena)
     srv = bls.bls_server_create(max_slots=8, arena_bytes=max(arena, 1 << 20))
+    try:
+        tickets = [_submit(bls, srv, lc) for lc in heavy_pts + heavy_per]
+        res = [bls.bls_server_wait(srv, tk, 60.0) for tk in tickets]
+        st = bls.bls_server_get_stats(srv)
+    finally:
+        bls.bls_server_destroy(srv)
+    assert all(r["status"] == bls.BLS_OK for r in res)
+    assert st["completed"] == len(tickets)
+    assert st["device_bytes_peak"] <= max(arena, 1 << 20)
+    for lc, r in zip([heavy_pts[0], heavy_per[-1]], [res[0], res[-1]]):
+        o = oracle.search(lc.t, lc.x, lc.w, lc.periods, lc.nbins, lc.qmin,
+                          lc.qmax)
+        check_curve(lc, r, o, label="arena mix")
+
+
+def test_small_arena_queues_instead_of_failing(bls):
+    reqs = _requests(10, 5252, n_range=(3000, 6000), np_range=(6000, 9000))
+    # a resident request holds 40 B per point and 24 B per period; the arena
+    # holds about two of the largest
+    need = max(_bytes(lc) for lc in reqs)
+    arena = max(int(need * 2.2), 1 << 20)   # the server's smallest arena
+    assert arena < 4 * need
+    _say("small arena", arena)
+    srv = bls.bls_server_create(max_slots=8, arena_bytes=arena)
     try:
         tickets = [_submit(bls, srv, lc) for lc in reqs]
         st0 = bls.bls_server_get_stats(srv)

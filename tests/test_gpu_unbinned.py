@@ -110,7 +110,10 @@ def _check(curve, per, g, o, tag):
     (37, 50, 0.05, 0.3, False),      # fewer points than a wave
     (257, 80, 0.01, 0.1, False),     # ragged against the block
     (1000, 120, 0.01, 0.1, True),
-    (4096, 12, 0.005, 0.02, False),  # the largest curve
+    (4096, 12, 0.005, 0.02, False),  # the largest curve held in LDS
+    (4097, 6, 0.005, 0.02, True),    # the smallest in the workspace
+    (10000, 6, 0.005, 0.03, False),  # workspace: uneven-batch sizes
+    (20000, 4, 0.005, 0.02, True),
     (600, 60, 0.2, 0.5, True),       # wide boxes
 ])
 def test_single_curves(bls, plan, n, nper, qmin, qmax, weighted):
@@ -157,10 +160,13 @@ def test_degenerate_and_errors(bls, plan):
     sr, depth, first, last, best = _gpu(bls, plan, [(t, x, None)], [per],
                                         0.01, 0.2)
     assert np.all(sr == 0) and np.all(first == -1) and np.all(last == -1)
-    lc = synth.small_curve(5, 4097, nperiods=3, nbins=64, qmin=0.01, qmax=0.1)
+    n_big = (1 << 20) + 1
+    t_big = synth.T_START + np.arange(n_big) / 1440.0
     _say("unbinned too long")
-    with pytest.raises(bls.BlsError) as ei:
-        _gpu(bls, plan, [(lc.t, lc.x, None)], [lc.periods], 0.01, 0.1)
+    with bls.Plan(max_points=n_big, max_periods=8) as pbig:
+        with pytest.raises(bls.BlsError) as ei:
+            _gpu(bls, pbig.handle, [(t_big, np.ones(n_big), None)], [per[:3]],
+                 0.01, 0.1)
     assert ei.value.status == bls.BLS_ERR_CAPACITY
     lc = synth.small_curve(6, 300, nperiods=5, nbins=64, qmin=0.01, qmax=0.1)
     for qmin, qmax in ((0.0, 0.1), (0.2, 0.1), (0.1, 1.0)):
