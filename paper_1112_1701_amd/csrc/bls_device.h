@@ -107,6 +107,10 @@ struct SearchArgs {
   // they are in LDS)
   unsigned char *uws;
   int64_t uws_stride;
+  // fold of the binned search: 0 merges a thread's same-bin points where the
+  // cadence makes that likely, 1 always, 2 never (equal results)
+  int32_t fold_policy;
+  int32_t pad_policy;
   // Work partitions: items [part_begin[x], part_begin[x+1]) belong to
   // partition x, which workgroups with blockIdx.x % nparts == x drain first
   // (workgroups are dispatched to the XCDs round-robin, so a partition's

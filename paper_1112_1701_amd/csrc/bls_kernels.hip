@@ -341,6 +341,17 @@ __device__ inline int fold_lane_gap(double fmin, int nbins, float cadence) {
   return !(x < 0.5) || !(x > 0.0) ? 1 : x >= 0.25 ? 2 : 4;
 }
 
+// Whether a tile's fold merges a thread's consecutive same-bin points: when
+// one cadence step advances the phase by less than a bin at the tile's
+// longest period (frequency fmin), unless the launch fixes the choice
+// (policy 1: always, 2: never).  Any answer is correct; this one only picks
+// the faster fold.
+__device__ inline bool fold_merges(double fmin, int nbins, float cadence, int policy) {
+  if (policy != 0) return policy == 1;
+  const double x = fmin * (double)nbins * (double)cadence;
+  return !(x >= 1.0);
+}
+
 // Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
 // Each thread takes kPPT consecutive points, so the 64 lanes of one atomic
 // instruction hold points kPPT apart in time: their phases (hence bins and
@@ -353,7 +364,10 @@ __device__ inline int fold_lane_gap(double fmin, int nbins, float cadence) {
 // Weighted curves use two such planes per period, A (count, weight) then B
 // (weighted signal), each contiguous so that the lanes of one atomic spread
 // over all LDS banks.
-template <bool WEIGHTED, bool FULL>
+// MERGE: consecutive points of a thread that share a bin are summed first;
+// without it every point is one atomic (tiles whose periods are short
+// against the cadence, where neighbours almost never share a bin).
+template <bool WEIGHTED, bool FULL, bool MERGE>
 __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int64_t base,
                                   int np, const double *s_f, unsigned long long *s_hist,
                                   int HS, int gap) {
@@ -406,6 +420,19 @@ __device__ inline void fold_chunk(const SearchArgs &a, const CurveDesc &cd, int6
     int bin[kPPT];
 #pragma unroll
     for (int r = 0; r < kPPT; ++r) bin[r] = raw_bin(d[r], f, nbd);
+    if (!MERGE) {
+#pragma unroll
+      for (int r = 0; r < kPPT; ++r) {
+        if (FULL || ok[r]) {
+          __hip_atomic_fetch_add(h + bin[r], va[r], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (WEIGHTED)
+            __hip_atomic_fetch_add(h + HS + bin[r], vb[r], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+      continue;
+    }
     unsigned long long accA = 0, accB = 0;
 #pragma unroll
     for (int r = 0; r < kPPT; ++r) {
@@ -451,60 +478,58 @@ __device__ __forceinline__ void consider(float R, float S, float C, float d, int
 
 // One lane task, unit weights: every width kmin..kmax from start bin j (h
 // points at bin j of the period's histogram; the wrap-around copy follows
-// the last bin).  Counts are exact integers in FP32, so d = W - R is kept
-// by subtraction and u = theta R by fused multiply-add; a box can beat
-// theta only if S^2 >= u d.  Boxes passing that screen get the exact test.
+// the last bin).  Counts are exact integers in FP32, so d = W - R is kept by
+// subtraction.  Widths are screened four at a time against theta: a box
+// beats theta only if S^2 >= theta R d, and over four consecutive widths
+// R d = R (W - R) is concave in the growing R, so its least value is at the
+// first or the last of the four, while S^2 is at most the largest of the
+// four |S|^2.  A group passing that bound is taken again box by box, each
+// box screened alone and, if it passes, given the exact test.
 template <bool DIP, bool MIP1>
 __device__ __forceinline__ void scan_task_unit(const float2 *h, int kmin, int kmax, float Wf,
                                                float thr, float mipf, float &bn, float &bd,
                                                int &bm) {
-  float d = Wf, S = 0.0f, u = 0.0f;
+  float d = Wf, S = 0.0f;
   int m = 0;
   for (; m < kmin - 1; ++m) {
     const float2 e = h[m];
     d -= e.x;
     S += e.y;
-    u = fmaf(thr, e.x, u);
   }
   bn = 0.0f;
   bd = 1.0f;
   bm = -1;
   for (; m + 4 <= kmax; m += 4) {
     const float2 e0 = h[m], e1 = h[m + 1], e2 = h[m + 2], e3 = h[m + 3];
-    const float d0 = d - e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
-    const float d1 = d0 - e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
-    const float d2 = d1 - e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
-    const float d3 = d2 - e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
-    // x = S^2 - u d; one comparison of the largest of the four decides
-    // whether any of them needs the exact test.
-    const float x0 = fmaf(-u0, d0, S0 * S0);
-    const float x1 = fmaf(-u1, d1, S1 * S1);
-    const float x2 = fmaf(-u2, d2, S2 * S2);
-    const float x3 = fmaf(-u3, d3, S3 * S3);
-    if (fmaxf(fmaxf(x0, x1), fmaxf(x2, x3)) >= 0.0f) {
+    const float d0 = d - e0.x, S0 = S + e0.y;
+    const float d1 = d0 - e1.x, S1 = S0 + e1.y;
+    const float d2 = d1 - e2.x, S2 = S1 + e2.y;
+    const float d3 = d2 - e3.x, S3 = S2 + e3.y;
+    const float sm = fmaxf(fmaxf(fabsf(S0), fabsf(S1)), fmaxf(fabsf(S2), fabsf(S3)));
+    const float g = fminf((Wf - d0) * d0, (Wf - d3) * d3);
+    if (sm * sm >= thr * g) {
       // Rare: the four boxes again from the group's start, in the same
-      // operations (so the same values), each to the exact test if it passed.
-      float dd = d, SS = S, uu = u;
+      // operations (so the same values).
+      float dd = d, SS = S;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float2 e = h[m + i];
         dd -= e.x;
         SS += e.y;
-        uu = fmaf(thr, e.x, uu);
-        if (fmaf(-uu, dd, SS * SS) >= 0.0f)
-          consider<false, DIP, MIP1>(Wf - dd, SS, 0.f, dd, m + i, 0.f, mipf, bn, bd, bm);
+        const float R = Wf - dd;
+        if (SS * SS >= thr * (R * dd))
+          consider<false, DIP, MIP1>(R, SS, 0.f, dd, m + i, 0.f, mipf, bn, bd, bm);
       }
     }
     d = d3;
     S = S3;
-    u = u3;
   }
   for (; m < kmax; ++m) {
     const float2 e = h[m];
     d -= e.x;
     S += e.y;
-    u = fmaf(thr, e.x, u);
-    if (S * S >= u * d) consider<false, DIP, MIP1>(Wf - d, S, 0.f, d, m, 0.f, mipf, bn, bd, bm);
+    const float R = Wf - d;
+    if (S * S >= thr * (R * d)) consider<false, DIP, MIP1>(R, S, 0.f, d, m, 0.f, mipf, bn, bd, bm);
   }
 }
 
@@ -535,61 +560,55 @@ __device__ __forceinline__ void consider_w(float R, float S, float d, int m, con
 
 // One lane task, weighted curves.  R is a running sum of the box's weight
 // (positive terms, so its relative error stays within k roundings) and
-// d = W - R is formed per box; u = theta R by fused multiply-add, so the
-// screen S^2 >= u d costs seven operations per box (ha: the period's (R, S)
-// bins from start j; hc: their counts in .x, read only for boxes that pass).
+// d = W - R is formed per box.  The screen is that of unit weights: R (W - R)
+// is concave in the growing R, so four consecutive widths are bounded by
+// the larger |S| of the four and the smaller R (W - R) of the first and the
+// last (ha: the period's (R, S) bins from start j; hc: their counts in .x,
+// read only for boxes that pass).
 template <bool DIP>
 __device__ __forceinline__ void scan_task_weighted(const float2 *ha, const float2 *hc, int kmin,
                                                    int kmax, float Wf, float thr, float nmax1,
                                                    float mipf, bool need_counts, float &bn,
                                                    float &bd, int &bm) {
-  float R = 0.0f, S = 0.0f, u = 0.0f;
+  float R = 0.0f, S = 0.0f;
   int m = 0;
   for (; m < kmin - 1; ++m) {
     const float2 e = ha[m];
     R += e.x;
     S += e.y;
-    u = fmaf(thr, e.x, u);
   }
   bn = 0.0f;
   bd = 1.0f;
   bm = -1;
   for (; m + 4 <= kmax; m += 4) {
     const float2 e0 = ha[m], e1 = ha[m + 1], e2 = ha[m + 2], e3 = ha[m + 3];
-    const float R0 = R + e0.x, S0 = S + e0.y, u0 = fmaf(thr, e0.x, u);
-    const float R1 = R0 + e1.x, S1 = S0 + e1.y, u1 = fmaf(thr, e1.x, u0);
-    const float R2 = R1 + e2.x, S2 = S1 + e2.y, u2 = fmaf(thr, e2.x, u1);
-    const float R3 = R2 + e3.x, S3 = S2 + e3.y, u3 = fmaf(thr, e3.x, u2);
-    // as for unit weights: the largest x = S^2 - u d of the four decides,
-    // and the rare boxes that pass are recomputed from the group's start
-    const float x0 = fmaf(-u0, Wf - R0, S0 * S0);
-    const float x1 = fmaf(-u1, Wf - R1, S1 * S1);
-    const float x2 = fmaf(-u2, Wf - R2, S2 * S2);
-    const float x3 = fmaf(-u3, Wf - R3, S3 * S3);
-    if (fmaxf(fmaxf(x0, x1), fmaxf(x2, x3)) >= 0.0f) {
-      float RR = R, SS = S, uu = u;
+    const float R0 = R + e0.x, S0 = S + e0.y;
+    const float R1 = R0 + e1.x, S1 = S0 + e1.y;
+    const float R2 = R1 + e2.x, S2 = S1 + e2.y;
+    const float R3 = R2 + e3.x, S3 = S2 + e3.y;
+    const float sm = fmaxf(fmaxf(fabsf(S0), fabsf(S1)), fmaxf(fabsf(S2), fabsf(S3)));
+    const float g = fminf(R0 * (Wf - R0), R3 * (Wf - R3));
+    if (sm * sm >= thr * g) {
+      float RR = R, SS = S;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float2 e = ha[m + i];
         RR += e.x;
         SS += e.y;
-        uu = fmaf(thr, e.x, uu);
         const float dd = Wf - RR;
-        if (fmaf(-uu, dd, SS * SS) >= 0.0f)
+        if (SS * SS >= thr * (RR * dd))
           consider_w<DIP>(RR, SS, dd, m + i, hc, need_counts, nmax1, mipf, bn, bd, bm);
       }
     }
     R = R3;
     S = S3;
-    u = u3;
   }
   for (; m < kmax; ++m) {
     const float2 e = ha[m];
     R += e.x;
     S += e.y;
-    u = fmaf(thr, e.x, u);
     const float d = Wf - R;
-    if (S * S >= u * d) consider_w<DIP>(R, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
+    if (S * S >= thr * (R * d)) consider_w<DIP>(R, S, d, m, hc, need_counts, nmax1, mipf, bn, bd, bm);
   }
 }
 
@@ -850,15 +869,23 @@ void search_kernel(SearchArgs a) {
     __syncthreads();
     // the tile's longest period, taken from its ends (period grids are
     // ordered in practice; another choice only changes the speed)
-    const int lanes_gap = __builtin_amdgcn_readfirstlane(
-        fold_lane_gap(fmin(s_f[0], s_f[np - 1]), cd.nbins, cd.cadence));
+    const double ftile = fmin(s_f[0], s_f[np - 1]);
+    const int lanes_gap =
+        __builtin_amdgcn_readfirstlane(fold_lane_gap(ftile, cd.nbins, cd.cadence));
+    // Merging a thread's same-bin points pays only where one cadence step
+    // moves the phase by less than a bin at the tile's longest period.
+    const bool merge = fold_merges(ftile, cd.nbins, cd.cadence, a.fold_policy);
 
     // Fold and bin: points in registers, reused for every period of the tile.
     for (int64_t base = 0; base < cd.n; base += (int64_t)kBlock * kPPT) {
-      if (base + (int64_t)kBlock * kPPT <= cd.n)
-        fold_chunk<WEIGHTED, true>(a, cd, base, np, s_f, s_hist, HS, lanes_gap);
-      else
-        fold_chunk<WEIGHTED, false>(a, cd, base, np, s_f, s_hist, HS, 1);
+      if (base + (int64_t)kBlock * kPPT <= cd.n) {
+        if (merge)
+          fold_chunk<WEIGHTED, true, true>(a, cd, base, np, s_f, s_hist, HS, lanes_gap);
+        else
+          fold_chunk<WEIGHTED, true, false>(a, cd, base, np, s_f, s_hist, HS, lanes_gap);
+      } else {
+        fold_chunk<WEIGHTED, false, true>(a, cd, base, np, s_f, s_hist, HS, 1);
+      }
     }
     __syncthreads();
 
@@ -923,9 +950,10 @@ void search_kernel(SearchArgs a) {
     // validity test and index bookkeeping.  The largest box always passes,
     // so the result is that of the full comparison.
     //
-    // The relaxation covers the rounding of u = theta R, an FMA chain of k
-    // non-negative terms (relative error below k 2^-24), and for weighted
-    // curves that of the running weight R itself; at least 2^-14.
+    // The relaxation covers the rounding of the screen's products (a few
+    // units of 2^-24), the departure of the rounded R (W - R) from a concave
+    // function of R, and for weighted curves the rounding of the running
+    // weight R itself (k terms); at least 2^-14.
     if (kmin <= kscan) {
       const float Wf = cd.Wf;
       const float nmax1 = (float)(cd.n_eff - 1);

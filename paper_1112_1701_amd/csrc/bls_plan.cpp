@@ -587,6 +587,9 @@ int enqueue_kernel(bls_plan *p, const PlannedBatch &pb, const double *periods, f
   sa.ucap = pb.ucap;
   sa.uws = pb.uws;
   sa.uws_stride = pb.uws_stride;
+  sa.fold_policy = 0;
+  sa.pad_policy = 0;
+  if (const char *fm = getenv("BLS_FOLD_MERGE")) sa.fold_policy = atoi(fm) == 1 ? 1 : 2;
   sa.nparts = pb.nparts;
   sa.pad_parts = 0;
   for (int x = 0; x <= kMaxParts; ++x) sa.part_begin[x] = pb.part_begin[x];

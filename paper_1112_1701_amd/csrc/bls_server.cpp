@@ -247,6 +247,8 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
   a.ucap = 0;
   a.uws = nullptr;
   a.uws_stride = 0;
+  a.fold_policy = 0;
+  a.pad_policy = 0;
   single_partition(a);
   const bool dip = (s->cfg.flags & BLS_DIP_ONLY) != 0;
   int per_cu = 1;
