@@ -51,9 +51,12 @@ struct Req {
   double pp = 0, evals = 0;
 };
 
+// One tick: period tiles of every kind of admitted request, unit-weight
+// segments first (nu of them), then weighted ones; each kind is its own
+// persistent launch of the tick, back to back on the server's stream.
 struct Tick {
   int buf = 0;
-  bool weighted = false;
+  int nu = 0;
   std::vector<TickSegment> segs;
 };
 
@@ -199,64 +202,76 @@ hipError_t start_request(bls_server *s, Req *r) {
   return (hipError_t)launch_prep(pa, st);
 }
 
-hipError_t launch_tick(bls_server *s, Tick &tk) {
-  const int b = tk.buf;
-  int64_t items = 0;
-  int hist_bytes = 0;
-  const int wpb = tk.weighted ? 2 : 1;
-  for (size_t i = 0; i < tk.segs.size(); ++i) {
-    const TickSegment &g = tk.segs[i];
-    s->h_seg_start[b][i] = items;
-    s->h_seg_curve[b][i] = g.slot;
-    s->h_seg_tile0[b][i] = g.tile0;
-    items += g.ntiles;
-    const Req *r = s->slots[g.slot];
-    hist_bytes = std::max(hist_bytes, r->tile * r->hstride * 8 * wpb);
-  }
-  const int nseg = (int)tk.segs.size();
-  s->h_seg_start[b][nseg] = items;
-  hipStream_t st = s->stream;
-  hipError_t e;
-  if ((e = hipMemcpyAsync(s->d_seg_start[b], s->h_seg_start[b], 8 * (nseg + 1),
-                          hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(s->d_seg_curve[b], s->h_seg_curve[b], 4 * nseg, hipMemcpyHostToDevice,
-                          st)) ||
-      (e = hipMemcpyAsync(s->d_seg_tile0[b], s->h_seg_tile0[b], 4 * nseg, hipMemcpyHostToDevice,
-                          st)))
-    return e;
-  if ((e = (hipError_t)launch_fill(s->d_counter[b], nullptr, 0, st))) return e;
+// One persistent launch over segments [s0, s0 + n) of the tick's arrays;
+// seg_start holds n + 1 entries from sbase.
+hipError_t launch_kind(bls_server *s, int b, bool weighted, int s0, int sbase, int n,
+                       int64_t items, int hist_bytes, unsigned long long *counter) {
+  if (n == 0 || items == 0) return hipSuccess;
   SearchArgs a;
+  memset(&a, 0, sizeof a);
   a.curves = s->d_curves;
   a.periods = s->d_per;
   a.dt = s->d_dt;
   a.q = s->d_q;
-  a.qw = tk.weighted ? s->d_qw : nullptr;
-  a.seg_start = s->d_seg_start[b];
-  a.seg_curve = s->d_seg_curve[b];
-  a.seg_tile0 = s->d_seg_tile0[b];
-  a.nseg = nseg;
+  a.qw = weighted ? s->d_qw : nullptr;
+  a.seg_start = s->d_seg_start[b] + sbase;
+  a.seg_curve = s->d_seg_curve[b] + s0;
+  a.seg_tile0 = s->d_seg_tile0[b] + s0;
+  a.nseg = n;
   a.min_in_points = s->cfg.min_in_points;
   a.nitems = items;
-  a.counter = s->d_counter[b];
+  a.counter = counter;
   a.sr = s->d_sr;
   a.depth = s->d_depth;
   a.jstart = s->d_js;
   a.kwidth = s->d_ks;
   a.best_key = s->d_keys;
   a.hist_bytes = hist_bytes;
-  a.ucap = 0;
-  a.uws = nullptr;
-  a.uws_stride = 0;
-  a.fold_policy = 0;
-  a.pad_policy = 0;
   single_partition(a);
   const bool dip = (s->cfg.flags & BLS_DIP_ONLY) != 0;
   int per_cu = 1;
-  if ((e = (hipError_t)search_blocks_per_cu(tk.weighted, dip, hist_bytes, &per_cu))) return e;
+  hipError_t e = (hipError_t)search_blocks_per_cu(weighted, dip, hist_bytes, &per_cu);
+  if (e != hipSuccess) return e;
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)s->num_cus *
                                                                           std::max(per_cu, 1)));
+  return (hipError_t)launch_search(a, weighted, dip, (int)grid, s->stream);
+}
+
+hipError_t launch_tick(bls_server *s, Tick &tk) {
+  const int b = tk.buf;
+  const int nseg = (int)tk.segs.size();
+  const int nu = tk.nu, nw = nseg - nu;
+  // seg_start: the unit-weight launch's nu + 1 entries, then the weighted
+  // launch's nw + 1; seg_curve and seg_tile0: nu, then nw entries
+  int64_t items[2] = {0, 0};
+  int hist[2] = {0, 0};
+  for (int i = 0; i < nseg; ++i) {
+    const TickSegment &g = tk.segs[i];
+    const int kind = i < nu ? 0 : 1;
+    s->h_seg_start[b][i + kind] = items[kind];
+    s->h_seg_curve[b][i] = g.slot;
+    s->h_seg_tile0[b][i] = g.tile0;
+    items[kind] += g.ntiles;
+    const Req *r = s->slots[g.slot];
+    hist[kind] = std::max(hist[kind], r->tile * r->hstride * 8 * (kind ? 2 : 1));
+  }
+  s->h_seg_start[b][nu] = items[0];
+  s->h_seg_start[b][nseg + 1] = items[1];
+  hipStream_t st = s->stream;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(s->d_seg_start[b], s->h_seg_start[b], 8 * (nseg + 2),
+                          hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(s->d_seg_curve[b], s->h_seg_curve[b], 4 * nseg, hipMemcpyHostToDevice,
+                          st)) ||
+      (e = hipMemcpyAsync(s->d_seg_tile0[b], s->h_seg_tile0[b], 4 * nseg, hipMemcpyHostToDevice,
+                          st)))
+    return e;
+  // eight counters: the unit-weight launch takes the first, the weighted the fifth
+  if ((e = (hipError_t)launch_fill(s->d_counter[b], nullptr, 0, st))) return e;
   if ((e = hipEventRecord(s->ev_s[b], st))) return e;
-  if ((e = (hipError_t)launch_search(a, tk.weighted, dip, (int)grid, st))) return e;
+  if ((e = launch_kind(s, b, false, 0, 0, nu, items[0], hist[0], s->d_counter[b]))) return e;
+  if ((e = launch_kind(s, b, true, nu, nu + 1, nw, items[1], hist[1], s->d_counter[b] + 4)))
+    return e;
   return hipEventRecord(s->ev_e[b], st);
 }
 
@@ -389,23 +404,20 @@ void scheduler(bls_server *s) {
     Tick tk;
     if (!s->buf_busy[next_buf]) {
       std::vector<SlotWork> work;
-      bool weighted = false, first = true;
-      uint64_t oldest = ~0ull;
-      for (Req *r : s->slots)
-        if (r && r->issued < r->ntiles && r->order < oldest) {
-          oldest = r->order;
-          weighted = r->weighted;
-          first = false;
-        }
-      if (!first) {
-        for (int i = 0; i < (int)s->slots.size(); ++i) {
-          Req *r = s->slots[i];
-          if (r && r->issued < r->ntiles && r->weighted == weighted)
-            work.push_back({i, r->order, r->ntiles, r->issued, r->item_cost});
-        }
+      for (int i = 0; i < (int)s->slots.size(); ++i) {
+        Req *r = s->slots[i];
+        if (r && r->issued < r->ntiles)
+          work.push_back({i, r->order, r->ntiles, r->issued, r->item_cost});
+      }
+      if (!work.empty()) {
         tk.buf = next_buf;
-        tk.weighted = weighted;
         tk.segs = build_tick(work, s->tick_cost, 1);
+        // unit-weight segments first: each kind is one launch of the tick
+        std::stable_partition(tk.segs.begin(), tk.segs.end(), [&](const TickSegment &g) {
+          return !s->slots[g.slot]->weighted;
+        });
+        tk.nu = 0;
+        for (const TickSegment &g : tk.segs) tk.nu += s->slots[g.slot]->weighted ? 0 : 1;
         for (const SlotWork &wk : work) s->slots[wk.slot]->issued = wk.next_tile;
         have_tick = !tk.segs.empty();
       }
@@ -527,12 +539,12 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
   for (auto &r : req)
     if ((e = device_alloc(r.ptr, r.bytes))) return fail(srv_hip(s, e, "allocate arena"));
   for (int b = 0; b < kTickBuffers; ++b) {
-    if ((e = device_alloc((void **)&s->d_seg_start[b], 8 * (M + 1))) ||
+    if ((e = device_alloc((void **)&s->d_seg_start[b], 8 * (M + 2))) ||
         (e = device_alloc((void **)&s->d_seg_curve[b], 4 * M)) ||
         (e = device_alloc((void **)&s->d_seg_tile0[b], 4 * M)) ||
         (e = device_alloc((void **)&s->d_counter[b], 64)))
       return fail(srv_hip(s, e, "allocate tick buffers"));
-    if ((e = hipHostMalloc((void **)&s->h_seg_start[b], 8 * (M + 1), 0)) ||
+    if ((e = hipHostMalloc((void **)&s->h_seg_start[b], 8 * (M + 2), 0)) ||
         (e = hipHostMalloc((void **)&s->h_seg_curve[b], 4 * M, 0)) ||
         (e = hipHostMalloc((void **)&s->h_seg_tile0[b], 4 * M, 0)))
       return fail(srv_hip(s, e, "allocate pinned tick buffers"));
