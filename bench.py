@@ -933,7 +933,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the search shards by curve with "
-              "no collective, and this build measures the single-GPU kernel "
+              "no collective, and bench.py measures the single-GPU kernel "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

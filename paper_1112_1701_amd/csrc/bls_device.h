@@ -182,6 +182,10 @@ struct WindowArgs {
 };
 constexpr int kMaxCycle = 1 << 29;
 
+// Eclipse-window workspace: per period the nphase bins, (min, max) cycle
+// numbers as two int32.
+constexpr int window_lds_bytes(int tile, int nphase) { return tile * nphase * 8; }
+
 int launch_window(const WindowArgs &a, int grid, void *stream);
 
 // High-variability pre-search.

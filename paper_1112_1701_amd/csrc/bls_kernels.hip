@@ -1391,15 +1391,145 @@ __global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
 constexpr int kCycleEmptyLo = 0x3fffffff;   // min of an empty bin
 constexpr int kCycleEmptyHi = -0x3fffffff;  // max of an empty bin
 
+// Integer wave sum through DPP moves (registers only): lanes exchange within
+// quads, half rows and rows, then rows are combined by row_bcast; lane 63
+// holds the total, which every lane receives.  Lanes a DPP step does not
+// write keep 0, so they add nothing.
+template <int CTRL, int ROWS>
+__device__ inline int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+
+__device__ inline int wave_isum(int v) {
+  v += dpp_i32<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_i32<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_i32<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_i32<0x140, 0xf>(v);  // row_mirror
+  v += dpp_i32<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_i32<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// The decision of every window of one period in one pass over its entries.
+// Entries are the nphase bins followed by the first k-1 bins again, one
+// cycle earlier (entry nb + b is bin b with its cycle numbers minus one), so
+// the window at offset j is the k entries j .. j+k-1 of E[0, L), L = nb+k-1.
+// A window holds two distinct eclipse numbers exactly when D(j) <= j+k-1,
+// where D(j) is the first entry at which its entries from j on hold two:
+//   NF(i)  first filled entry >= i;
+//   B(p)   filled p that is mixed (min < max), or whose previous filled
+//          entry is mixed or has another cycle number;
+//   NB(i)  first p >= i with B(p);
+//   G(f)   f if f is mixed, else NB(f+1) (the filled entries between are
+//          single-valued with f's number, and NB(f+1) is the first that is
+//          not);
+//   D(j) = G(NF(j)).
+// With one eclipse required every filled entry counts as mixed, and D(j) =
+// NF(j).  D(j) >= j, and no window reaches past L-1, so entries from L on
+// (read from any bin) decide nothing.
+//
+// One wave takes the period: lane l owns the s consecutive entries
+// [l s, l s + s), s odd so that the lanes' strided reads spread over the
+// LDS banks.  The lane walks its entries downwards keeping the next filled
+// entry p: at a filled entry q, B(p) follows from p and q alone (q is p's
+// previous filled entry), so NB(q+1) is p when B(p), else NB(p+1), and G(q)
+// follows.  Above the lane's last filled entry NB is NB past the lane,
+// carried as kWinOut until a wave scan supplies it.  Three wave scans join
+// the lanes: the last filled entry of the lanes before (for the B of the
+// lane's first filled entry), NB past the lane (a suffix minimum of the
+// lanes' first B), and the G of the first filled entry after the lane (for
+// the windows after its last filled entry).
+constexpr int kWinInf = 0x3fffffff;   // no such entry
+constexpr int kWinOut = 0x3ffffffe;   // NB past the lane, not yet known
+
+__device__ __forceinline__ int window_period(const int2 *row, int nb, int k, int gap) {
+  const int lane = threadIdx.x & 63;
+  const int L = nb + k - 1;
+  const int s = ((L + 63) >> 6) | 1;
+  const int base = lane * s;
+  const int ng = 1 - gap;
+  // the next filled entry (none yet: p_mx = 1 makes the first one found
+  // take NB(q+1) = p_pos = kWinOut)
+  int p_pos = kWinOut, p_lo = 0, p_mx = 1, p_nb = kWinOut;
+  int g = kWinInf;      // G of the next filled entry = D of the entries so far
+  int last = -1;        // the lane's last filled entry
+  int olo = kWinInf;    // lowest entry whose D is NB past the lane
+  int cnt = 0;
+  for (int m = s - 1; m >= 0; --m) {
+    const int x = base + m;
+    const int wrap = x >= nb ? 1 : 0;
+    const int2 v = row[min(x - wrap * nb, nb - 1)];
+    const bool fl = v.x <= v.y;
+    const int mx = v.x < v.y + ng ? 1 : 0;
+    const int lo = v.x - wrap;
+    const int nq = (p_mx | mx | (p_lo ^ lo)) ? p_pos : p_nb;
+    const int gq = mx ? x : nq;
+    p_pos = fl ? x : p_pos;
+    p_lo = fl ? lo : p_lo;
+    p_mx = fl ? mx : p_mx;
+    p_nb = fl ? nq : p_nb;
+    g = fl ? gq : g;
+    last = max(last, fl ? x : -1);
+    olo = g == kWinOut ? x : olo;
+    cnt += g < x + (x < nb ? k : 0) ? 1 : 0;
+  }
+  // the lane's first filled entry is p (G(p) = g), its last one `last`
+  const bool any = last >= 0;
+  int l_lo = 0, l_mx = 0;
+  if (any) {
+    const int wrap = last >= nb ? 1 : 0;
+    const int2 v = row[last - wrap * nb];
+    l_lo = v.x - wrap;
+    l_mx = v.x < v.y + ng ? 1 : 0;
+  }
+  // the last filled entry of the lanes before: cycle number + 1, shifted,
+  // with the mixed flag in bit 0 (-1: none)
+  int xs = any ? (((l_lo + 1) << 1) | l_mx) : -1;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(xs, d, 64);
+    if (lane >= d && xs < 0) xs = y;
+  }
+  int carry = __shfl_up(xs, 1, 64);
+  if (lane == 0) carry = -1;
+  const bool bf = any && (p_mx || (carry >= 0 && ((carry & 1) || (carry >> 1) - 1 != p_lo)));
+  // the lane's first B: its first filled entry, or NB past it
+  int nbx = bf ? p_pos : (any && p_nb != kWinOut ? p_nb : kWinInf);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_down(nbx, d, 64);
+    if (lane + d < 64) nbx = min(nbx, y);
+  }
+  int nb_out = __shfl_down(nbx, 1, 64);
+  if (lane == 63) nb_out = kWinInf;
+  // entries olo .. last have D = NB past the lane
+  if (any && olo <= last && nb_out < kWinInf)
+    cnt += max(0, min(last + 1, nb) - max(olo, nb_out - k + 1));
+  // the entries after the last filled one have D = G of the next filled
+  // entry of the lanes after
+  int gx = any ? (g == kWinOut ? nb_out : g) : -1;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_down(gx, d, 64);
+    if (lane + d < 64 && gx < 0) gx = y;
+  }
+  int gc = __shfl_down(gx, 1, 64);
+  if (lane == 63) gc = -1;
+  if (gc >= 0 && gc < kWinInf)
+    cnt += max(0, min(base + s, nb) - max(max(last + 1, base), gc - k + 1));
+  return wave_isum(cnt);
+}
+
 __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
   extern __shared__ int2 s_mm[];            // [tile][nphase] (min, max cycle)
   __shared__ double s_f[kTileMax];
   __shared__ int s_k[kTileMax];
-  __shared__ int s_count[kTileMax];
   const int tid = threadIdx.x;
   const int nb = a.nphase;
   const double nbd = (double)nb;
   const unsigned nbm1 = (unsigned)(nb - 1);
+  const int gap = a.min_eclipses >= 2 ? 1 : 0;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
   // A workgroup's items increase, so its cadence only moves forward: keep
   // the current one and the first item of the next.
@@ -1432,24 +1562,21 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
       const double kr = __builtin_round(a.duration * f * nbd);
       s_f[tid] = f;
       s_k[tid] = kr < 1.0 ? 1 : kr > nbd ? nb : (int)kr;
-      s_count[tid] = 0;
     }
     for (int i = tid; i < np * nb; i += kBlock) s_mm[i] = make_int2(kCycleEmptyLo, kCycleEmptyHi);
     __syncthreads();
 
     // Fold: cycle numbers per bin.
     bool over = false;
-    auto fold_point = [&](double d) {
-      for (int t = 0; t < np; ++t) {
-        const double cyc = d * s_f[t];
-        const double e = floor(cyc);
-        const int b = (int)min((unsigned)(int)(__builtin_amdgcn_fract(cyc) * nbd), nbm1);
-        over |= e >= (double)kMaxCycle;
-        const int ei = e >= (double)kMaxCycle ? kMaxCycle : (int)e;
-        int *w2 = reinterpret_cast<int *>(s_mm + t * nb + b);
-        atomicMin(w2, ei);
-        atomicMax(w2 + 1, ei);
-      }
+    auto fold_point = [&](double d, double f, int2 *row) {
+      const double cyc = d * f;
+      const double e = floor(cyc);
+      const int b = (int)min((unsigned)(int)(__builtin_amdgcn_fract(cyc) * nbd), nbm1);
+      over |= e >= (double)kMaxCycle;
+      const int ei = e >= (double)kMaxCycle ? kMaxCycle : (int)e;
+      int *w2 = reinterpret_cast<int *>(row + b);
+      atomicMin(w2, ei);
+      atomicMax(w2 + 1, ei);
     };
     if (wd.n <= (int64_t)kBlock * kWinRegs) {
       if (cached != cur) {
@@ -1463,78 +1590,31 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
         }
         cached = cur;
       }
+      for (int t = 0; t < np; ++t) {
+        const double f = s_f[t];
 #pragma unroll
-      for (int r = 0; r < kWinRegs; ++r)
-        if (kreg[r]) fold_point(dreg[r]);
+        for (int r = 0; r < kWinRegs; ++r)
+          if (kreg[r]) fold_point(dreg[r], f, s_mm + t * nb);
+      }
     } else {
-      for (int64_t i = tid; i < wd.n; i += kBlock) {
-        const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
-        if (wi == 0.0) continue;
-        fold_point(a.t[wd.n_off + i] - wd.t0);
+      for (int t = 0; t < np; ++t) {
+        const double f = s_f[t];
+        for (int64_t i = tid; i < wd.n; i += kBlock) {
+          const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
+          if (wi == 0.0) continue;
+          fold_point(a.t[wd.n_off + i] - wd.t0, f, s_mm + t * nb);
+        }
       }
     }
     if (over) atomicOr(a.overflow, 1u);
     __syncthreads();
 
-    // Scan: one task per (period, offset), windows of k bins.
-    const int need2 = a.min_eclipses >= 2;
-    // Tasks tid, tid + kBlock, ... as (period t, offset j), stepped without
-    // a division (nb >= 2, so one subtraction may not suffice: loop).
-    int t = 0, j = tid;
-    while (j >= nb) {
-      j -= nb;
-      ++t;
+    // Windows: one wave per period.
+    for (int t = wave; t < np; t += kBlock / 64) {
+      const int k = __builtin_amdgcn_readfirstlane(s_k[t]);
+      const int c = window_period(s_mm + t * nb, nb, k, gap);
+      if ((tid & 63) == 0) out[t] = c;
     }
-    for (int task = tid; task < np * nb; task += kBlock) {
-      const int k = s_k[t];
-      const int2 *h = s_mm + t * nb;
-      // The window is decided as soon as it holds the required eclipses:
-      // lo/hi only move apart, so stop there.  Bins are read four at a
-      // time (their loads in flight together) and the test made per group.
-      int lo_c = kCycleEmptyLo, hi_c = kCycleEmptyHi;
-      const int gap = need2 ? 1 : 0;
-      const int first = min(k, nb - j);      // bins j .. nb-1, same cycle
-      const int2 empty = make_int2(kCycleEmptyLo, kCycleEmptyHi);
-      for (int m = 0; m < first && hi_c - lo_c < gap; m += 4) {
-        const int2 *q = h + j + m;
-        const int2 v0 = q[0];
-        const int2 v1 = m + 1 < first ? q[1] : empty;
-        const int2 v2 = m + 2 < first ? q[2] : empty;
-        const int2 v3 = m + 3 < first ? q[3] : empty;
-        lo_c = min(min(lo_c, v0.x), min(min(v1.x, v2.x), v3.x));
-        hi_c = max(max(hi_c, v0.y), max(max(v1.y, v2.y), v3.y));
-      }
-      const int wrap = k - first;            // wrapped bins: one cycle earlier
-      for (int m = 0; m < wrap && hi_c - lo_c < gap; m += 4) {
-        const int2 v0 = h[m];
-        const int2 v1 = m + 1 < wrap ? h[m + 1] : empty;
-        const int2 v2 = m + 2 < wrap ? h[m + 2] : empty;
-        const int2 v3 = m + 3 < wrap ? h[m + 3] : empty;
-        lo_c = min(lo_c, min(min(v0.x, v1.x), min(v2.x, v3.x)) - 1);
-        hi_c = max(hi_c, max(max(v0.y, v1.y), max(v2.y, v3.y)) - 1);
-      }
-      const bool seen = hi_c - lo_c >= gap;
-      // Count per wave: one LDS add per period present among the active
-      // lanes (a wave's tasks span one or two periods), not one per lane on
-      // the same counter.
-      const unsigned long long hit = __ballot(seen);
-      unsigned long long pending = __ballot(1);
-      while (pending) {
-        const int lead = __ffsll((long long)pending) - 1;
-        const int tl = __shfl(t, lead, 64);
-        const unsigned long long same = __ballot(t == tl) & pending;
-        if ((int)(threadIdx.x & 63) == lead && (hit & same))
-          atomicAdd(&s_count[tl], __popcll(hit & same));
-        pending &= ~same;
-      }
-      j += kBlock;
-      while (j >= nb) {
-        j -= nb;
-        ++t;
-      }
-    }
-    __syncthreads();
-    if (tid < np) out[tid] = s_count[tid];
     }  // valid cadence
     __syncthreads();
   }
@@ -1553,10 +1633,6 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
 // 1 and row 2 into row 3 (row_bcast:15), then rows 0-1 into rows 2-3
 // (row_bcast:31); lane 63 holds the total, which is read out to every lane.
 // Lanes a DPP step does not write keep 0, so they add nothing.
-template <int CTRL, int ROWS>
-__device__ inline int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
-}
 
 template <int CTRL, int ROWS>
 __device__ inline double dpp_f64(double v) {
@@ -1579,15 +1655,6 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ inline int wave_isum(int v) {
-  v += dpp_i32<0xb1, 0xf>(v);
-  v += dpp_i32<0x4e, 0xf>(v);
-  v += dpp_i32<0x141, 0xf>(v);
-  v += dpp_i32<0x140, 0xf>(v);
-  v += dpp_i32<0x142, 0xa>(v);
-  v += dpp_i32<0x143, 0xc>(v);
-  return __builtin_amdgcn_readlane(v, 63);
-}
 
 // Sums over each half of a wave (lanes 0-31 and 32-63) in a fixed order:
 // the steps of wave_sum up to row_bcast:15, which leave the halves' totals
@@ -2256,11 +2323,13 @@ int launch_window(const WindowArgs &a, int grid, void *stream) {
                      a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.nitems <= 0) return (int)e;
-  const int lds = a.tile * a.nphase * (int)sizeof(int2);
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&window_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int lds = window_lds_bytes(a.tile, a.nphase);
+  const void *fn = reinterpret_cast<const void *>(&window_kernel);
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(window_kernel, dim3(grid), dim3(kBlock), (size_t)lds, (hipStream_t)stream, a);
+  void *args[] = {const_cast<WindowArgs *>(&a)};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)lds, (hipStream_t)stream);
+  if (e != hipSuccess) return (int)e;
   return (int)hipGetLastError();
 }
 

@@ -1298,9 +1298,10 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
       (!b->p_off && b->nperiods_shared < 1))
     return set_error(p, BLS_ERR_INVALID_ARG, "n_off[0] and p_off[0] must be 0, grid non-empty");
   const int nc = b->ncurves;
-  // 16 KB of (min, max) words per workgroup: eight or more workgroups per
-  // CU to overlap the per-item latencies
-  const int tile = std::max(1, std::min(kTileMax, (16 << 10) / (nphase * 8)));
+  // up to 32 KB of (min, max) words per workgroup (four periods at 1000
+  // phase bins, one per wave in the window pass): five workgroups per CU
+  const int tile =
+      std::max(1, std::min(kTileMax, (32 << 10) / window_lds_bytes(1, nphase)));
   std::vector<WindowDesc> wd(nc);
   int64_t items = 0, results = 0;
   for (int c = 0; c < nc; ++c) {
@@ -1335,7 +1336,7 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
       return hip_error(p, e, "allocate eclipse-window buffers");
     }
   }
-  const int lds = tile * nphase * 8;
+  const int lds = window_lds_bytes(tile, nphase);
   int per_cu = 0;
   if ((e = (hipError_t)window_blocks_per_cu(lds, &per_cu)) != hipSuccess)
     return hip_error(p, e, "window occupancy");

@@ -66,7 +66,10 @@ def _cadences(seed, k):
 
 @pytest.mark.parametrize("nphase,dur,m", [(16, 0.05, 2), (64, 0.02, 1),
                                           (300, 0.02, 2), (1000, 0.01, 2),
-                                          (1000, 0.3, 1), (4096, 0.02, 2)])
+                                          (1000, 0.3, 1), (1000, 0.3, 2),
+                                          (333, 0.5, 2), (2048, 0.05, 2),
+                                          (4096, 0.02, 2), (4096, 0.9, 2),
+                                          (2, 0.05, 2), (127, 0.03, 1)])
 def test_shared_grid_bit_exact(bls, plan, nphase, dur, m):
     ts = _cadences(200 + nphase, 10)
     t, n_off = _pack(ts)
@@ -74,6 +77,25 @@ def test_shared_grid_bit_exact(bls, plan, nphase, dur, m):
     per = np.sort(np.concatenate([synth.log_period_grid(0.1, 10.0, 397),
                                   [0.5, 1.0, 2.0]]))
     _say("window shared", nphase, dur, m, per.size, n_off[-1])
+    g = _gpu(bls, plan, t, n_off, per, None, nphase, dur, m)
+    for c, tc in enumerate(ts):
+        o = oracle.eclipse_window(tc, None, per, nphase, dur, m)
+        gc = g[c * per.size:(c + 1) * per.size]
+        assert np.array_equal(gc, o), (c, np.flatnonzero(gc != o)[:5])
+
+
+@pytest.mark.parametrize("nphase,dur,m", [(1000, 0.02, 2), (1000, 0.02, 1),
+                                          (250, 0.2, 2)])
+def test_dense_and_sparse_cadences(bls, plan, nphase, dur, m):
+    # continuous 1-minute sampling over 5 days (every bin filled, most
+    # holding several cycles; more points than the register cache), three
+    # exposures, and two on one night
+    ts = [synth.T_START + np.arange(7200) / 1440.0,
+          synth.T_START + np.array([0.1, 3.7, 9.2]),
+          synth.T_START + np.array([0.2, 0.21])]
+    t, n_off = _pack(ts)
+    per = synth.log_period_grid(0.1, 10.0, 301)
+    _say("window dense/sparse", nphase, dur, m)
     g = _gpu(bls, plan, t, n_off, per, None, nphase, dur, m)
     for c, tc in enumerate(ts):
         o = oracle.eclipse_window(tc, None, per, nphase, dur, m)
