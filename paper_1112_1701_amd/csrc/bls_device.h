@@ -183,8 +183,15 @@ struct WindowArgs {
 constexpr int kMaxCycle = 1 << 29;
 
 // Eclipse-window workspace: per period the nphase bins, (min, max) cycle
-// numbers as two int32.
-constexpr int window_lds_bytes(int tile, int nphase) { return tile * nphase * 8; }
+// numbers as two int32, then padding: the window pass reads up to s - 2
+// entries past a period's wrapped copy without using them, s the entries
+// per lane (at most the value below, for windows of nphase bins).
+constexpr int window_pad(int nphase) { return ((2 * nphase - 1 + 63) >> 6) | 1; }
+constexpr int window_lds_bytes(int tile, int nphase) {
+  return (tile * nphase + window_pad(nphase)) * 8;
+}
+// Static LDS of the window kernel (period frequencies and window lengths).
+constexpr int kWindowStaticLds = kTileMax * (8 + 4);
 
 int launch_window(const WindowArgs &a, int grid, void *stream);
 

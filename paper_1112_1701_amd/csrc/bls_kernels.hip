@@ -1442,12 +1442,19 @@ __device__ inline int wave_isum(int v) {
 constexpr int kWinInf = 0x3fffffff;   // no such entry
 constexpr int kWinOut = 0x3ffffffe;   // NB past the lane, not yet known
 
-__device__ __forceinline__ int window_period(const int2 *row, int nb, int k, int gap) {
+template <int GAP>
+__device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
   const int lane = threadIdx.x & 63;
   const int L = nb + k - 1;
   const int s = ((L + 63) >> 6) | 1;
   const int base = lane * s;
-  const int ng = 1 - gap;
+  // Lane nb / s holds entry nb at offset nb % s: above that offset the
+  // lanes from it on hold wrapped entries, below it those after it.  Within
+  // each part a lane's entries are all wrapped or none are, so cycle numbers
+  // are compared as stored and the next filled entry's number is moved into
+  // the unwrapped frame where the lane crosses.
+  const int sl = nb / s, mc = nb - sl * s;
+  const int wa = lane >= sl ? 1 : 0, wb = lane > sl ? 1 : 0;
   // the next filled entry (none yet: p_mx = 1 makes the first one found
   // take NB(q+1) = p_pos = kWinOut)
   int p_pos = kWinOut, p_lo = 0, p_mx = 1, p_nb = kWinOut;
@@ -1455,32 +1462,44 @@ __device__ __forceinline__ int window_period(const int2 *row, int nb, int k, int
   int last = -1;        // the lane's last filled entry
   int olo = kWinInf;    // lowest entry whose D is NB past the lane
   int cnt = 0;
-  for (int m = s - 1; m >= 0; --m) {
+  auto step = [&](int m, const int2 *r, int kk) {
     const int x = base + m;
-    const int wrap = x >= nb ? 1 : 0;
-    const int2 v = row[min(x - wrap * nb, nb - 1)];
+    const int2 v = r[x];
     const bool fl = v.x <= v.y;
-    const int mx = v.x < v.y + ng ? 1 : 0;
-    const int lo = v.x - wrap;
-    const int nq = (p_mx | mx | (p_lo ^ lo)) ? p_pos : p_nb;
-    const int gq = mx ? x : nq;
+    const bool mxb = GAP ? v.x < v.y : fl;
+    const int mx = mxb ? 1 : 0;
+    const int nq = (p_mx | mx | (p_lo ^ v.x)) ? p_pos : p_nb;
+    const int gq = mxb ? x : nq;
     p_pos = fl ? x : p_pos;
-    p_lo = fl ? lo : p_lo;
+    p_lo = fl ? v.x : p_lo;
     p_mx = fl ? mx : p_mx;
     p_nb = fl ? nq : p_nb;
     g = fl ? gq : g;
     last = max(last, fl ? x : -1);
     olo = g == kWinOut ? x : olo;
-    cnt += g < x + (x < nb ? k : 0) ? 1 : 0;
-  }
+    cnt += g < x + kk ? 1 : 0;
+  };
+  // wrapped entries x read bin x - nb; entries from L on decide nothing:
+  // a lane holding only such entries reads the first s bins, the lane
+  // holding entry L reads up to s - 2 entries past the period's wrapped
+  // copy (into the next period or the workspace's padding).  Only unwrapped
+  // entries start windows.
+  const bool idle = base >= L;
+  const int2 *ra = row - (idle ? base : wa * nb), *rb = row - (idle ? base : wb * nb);
+  const int ka = wa ? 0 : k, kb = wb ? 0 : k;
+  for (int m = s - 1; m >= mc; --m) step(m, ra, ka);
+  p_lo -= wa - wb;
+  for (int m = mc - 1; m >= 0; --m) step(m, rb, kb);
+  p_lo -= wb;
   // the lane's first filled entry is p (G(p) = g), its last one `last`
   const bool any = last >= 0;
   int l_lo = 0, l_mx = 0;
   if (any) {
+    // (an entry from L on, read from any bin, decides nothing)
     const int wrap = last >= nb ? 1 : 0;
-    const int2 v = row[last - wrap * nb];
+    const int2 v = row[min(last - wrap * nb, nb - 1)];
     l_lo = v.x - wrap;
-    l_mx = v.x < v.y + ng ? 1 : 0;
+    l_mx = (GAP ? v.x < v.y : true) ? 1 : 0;
   }
   // the last filled entry of the lanes before: cycle number + 1, shifted,
   // with the mixed flag in bit 0 (-1: none)
@@ -1520,15 +1539,16 @@ __device__ __forceinline__ int window_period(const int2 *row, int nb, int k, int
   return wave_isum(cnt);
 }
 
+template <int GAP>
 __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
-  extern __shared__ int2 s_mm[];            // [tile][nphase] (min, max cycle)
+  extern __shared__ int2 s_mm[];            // [tile][nphase] (min, max cycle), padding
   __shared__ double s_f[kTileMax];
   __shared__ int s_k[kTileMax];
+  static_assert(sizeof(s_f) + sizeof(s_k) == kWindowStaticLds, "window kernel static LDS");
   const int tid = threadIdx.x;
   const int nb = a.nphase;
   const double nbd = (double)nb;
   const unsigned nbm1 = (unsigned)(nb - 1);
-  const int gap = a.min_eclipses >= 2 ? 1 : 0;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
   // A workgroup's items increase, so its cadence only moves forward: keep
@@ -1612,7 +1632,7 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
     // Windows: one wave per period.
     for (int t = wave; t < np; t += kBlock / 64) {
       const int k = __builtin_amdgcn_readfirstlane(s_k[t]);
-      const int c = window_period(s_mm + t * nb, nb, k, gap);
+      const int c = window_period<GAP>(s_mm + t * nb, nb, k);
       if ((tid & 63) == 0) out[t] = c;
     }
     }  // valid cadence
@@ -2324,7 +2344,8 @@ int launch_window(const WindowArgs &a, int grid, void *stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.nitems <= 0) return (int)e;
   const int lds = window_lds_bytes(a.tile, a.nphase);
-  const void *fn = reinterpret_cast<const void *>(&window_kernel);
+  const void *fn = a.min_eclipses >= 2 ? reinterpret_cast<const void *>(&window_kernel<1>)
+                                       : reinterpret_cast<const void *>(&window_kernel<0>);
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return (int)e;
   void *args[] = {const_cast<WindowArgs *>(&a)};
@@ -2346,7 +2367,7 @@ int launch_variability(const VarArgs &a, void *stream) {
 }
 
 int window_blocks_per_cu(int lds_bytes, int *blocks) {
-  const void *fn = reinterpret_cast<const void *>(&window_kernel);
+  const void *fn = reinterpret_cast<const void *>(&window_kernel<1>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return (int)e;
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);

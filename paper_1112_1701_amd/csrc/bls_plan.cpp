@@ -1298,10 +1298,11 @@ int bls_eclipse_window_device(bls_plan *p, const bls_batch *b, int32_t nphase, d
       (!b->p_off && b->nperiods_shared < 1))
     return set_error(p, BLS_ERR_INVALID_ARG, "n_off[0] and p_off[0] must be 0, grid non-empty");
   const int nc = b->ncurves;
-  // up to 32 KB of (min, max) words per workgroup (four periods at 1000
-  // phase bins, one per wave in the window pass): five workgroups per CU
-  const int tile =
-      std::max(1, std::min(kTileMax, (32 << 10) / window_lds_bytes(1, nphase)));
+  // up to 32 KB of LDS per workgroup (four periods at 1000 phase bins, one
+  // per wave in the window pass): five workgroups per CU
+  const int tile = std::max(
+      1, std::min(kTileMax, ((32 << 10) - kWindowStaticLds - 8 * window_pad(nphase)) /
+                                (8 * nphase)));
   std::vector<WindowDesc> wd(nc);
   int64_t items = 0, results = 0;
   for (int c = 0; c < nc; ++c) {
