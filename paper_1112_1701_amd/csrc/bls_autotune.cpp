@@ -139,7 +139,7 @@ double time_candidate(bls_plan *p, std::vector<CurveShape> &shapes, bool weighte
   a.uws = nullptr;
   a.uws_stride = 0;
   a.fold_policy = 0;
-  a.pad_policy = 0;
+  a.seed_unit = 1;
   single_partition(a);
   const bool dip = (p->cfg.flags & BLS_DIP_ONLY) != 0;
   double best = 1e30;

@@ -110,7 +110,9 @@ struct SearchArgs {
   // fold of the binned search: 0 merges a thread's same-bin points where the
   // cadence makes that likely, 1 always, 2 never (equal results)
   int32_t fold_policy;
-  int32_t pad_policy;
+  // unit weights: seed each period's best with a few boxes before the scan
+  // (1) or start the scan from zero (0); equal results
+  int32_t seed_unit;
   // Work partitions: items [part_begin[x], part_begin[x+1]) belong to
   // partition x, which workgroups with blockIdx.x % nparts == x drain first
   // (workgroups are dispatched to the XCDs round-robin, so a partition's
@@ -162,6 +164,7 @@ struct WindowDesc {
   int32_t nperiods;
   int32_t check_periods;  // 1: the prep pass checks this cadence's periods
   double t0;            // min kept time (written on the device)
+  double dmax;          // max kept time - t0 (written on the device)
   int32_t status;       // CurveStatus (written on the device)
   int32_t pad;
 };

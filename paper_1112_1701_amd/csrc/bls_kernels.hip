@@ -700,6 +700,33 @@ __device__ inline void seed_best_weighted(const unsigned long long *s_hist,
   }
 }
 
+// The same seed for unit weights: kSeeds boxes of width kmin, each summed
+// and tested exactly as a lane task sums and tests it (d by subtraction
+// from W, S by addition, in bin order).
+template <bool DIP, bool MIP1>
+__device__ inline void seed_best_unit(const unsigned long long *s_hist,
+                                      unsigned long long *s_best, int np, int nb, int HS,
+                                      int kmin, float Wf, float mipf) {
+  for (int q = threadIdx.x; q < np * kSeeds; q += kBlock) {
+    const int t = q / kSeeds;
+    const int j = (int)(__umul24((unsigned)(q % kSeeds), (unsigned)nb) / kSeeds);
+    const float2 *h =
+        reinterpret_cast<const float2 *>(s_hist) + __umul24((unsigned)t, (unsigned)HS) + j;
+    float d = Wf, S = 0.0f;
+    for (int i = 0; i < kmin; ++i) {
+      const float2 e = h[i];
+      d -= e.x;
+      S += e.y;
+    }
+    float bn = 0.0f, bd = 1.0f;
+    int bm = -1;
+    consider<false, DIP, MIP1>(Wf - d, S, 0.f, d, kmin - 1, 0.f, mipf, bn, bd, bm);
+    if (bm >= 0)
+      __hip_atomic_fetch_max(&s_best[t], box_key(bn, bd, bm, j, nb), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 // Next work item of a persistent workgroup (thread 0 only): items of its
 // own partition first, then of the others in turn; -1 once all are taken.
 // done_mask remembers the partitions found empty.
@@ -940,6 +967,13 @@ void search_kernel(SearchArgs a) {
       seed_best_weighted<DIP>(s_hist, s_best, s_nonempty, np, nb, HS, kmin, kmax, cd.Wf,
                               (float)(cd.n_eff - 1), (float)a.min_in_points,
                               a.min_in_points <= 1);
+      __syncthreads();
+    } else if (!WEIGHTED && kmin <= kscan && a.seed_unit) {
+      if (a.min_in_points <= 1)
+        seed_best_unit<DIP, true>(s_hist, s_best, np, nb, HS, kmin, cd.Wf, 0.f);
+      else
+        seed_best_unit<DIP, false>(s_hist, s_best, np, nb, HS, kmin, cd.Wf,
+                                   (float)a.min_in_points);
       __syncthreads();
     }
 
@@ -1353,7 +1387,7 @@ __global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
   WindowDesc *wd = a.desc + c;
   const int64_t off = wd->n_off, n = wd->n;
   const int tid = threadIdx.x;
-  double tmin = INFINITY, bad = 0.0, kept = 0.0;
+  double tmin = INFINITY, tmax = -INFINITY, bad = 0.0, kept = 0.0;
   for (int64_t i = tid; i < n; i += kBlock) {
     const double wi = a.w ? a.w[off + i] : 1.0;
     if (!(wi >= 0.0) || isinf(wi)) {
@@ -1368,6 +1402,7 @@ __global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
     }
     kept = kept + 1.0;
     tmin = fmin(tmin, ti);
+    tmax = fmax(tmax, ti);
   }
   double badp = 0.0;
   if (wd->check_periods) {
@@ -1379,8 +1414,11 @@ __global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
   block_sum2(bad, kept, sa, sb);
   double mx = badp;
   block_minmax(tmin, mx, sa, sb);
+  double lo = INFINITY;
+  block_minmax(lo, tmax, sa, sb);
   if (tid == 0) {
     wd->t0 = tmin;
+    wd->dmax = tmax - tmin;
     wd->status = bad > 0.0 ? kCurveBadData
                  : kept < 1.0 ? kCurveTooFew
                  : mx > 0.0 ? kCurveBadPeriod
@@ -1441,6 +1479,11 @@ __device__ inline int wave_isum(int v) {
 // the windows after its last filled entry).
 constexpr int kWinInf = 0x3fffffff;   // no such entry
 constexpr int kWinOut = 0x3ffffffe;   // NB past the lane, not yet known
+// A filled entry's key: its cycle number when single-valued, kWinMix + its
+// position when mixed, so that B(p) (seen from p's previous filled entry q)
+// is key(p) != key(q).  Cycle numbers are at most kMaxCycle < kWinMix.
+constexpr int kWinMix = 0x40000000;
+constexpr int kWinNone = -0x7fffffff;  // no filled entry
 
 template <int GAP>
 __device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
@@ -1455,9 +1498,9 @@ __device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
   // the unwrapped frame where the lane crosses.
   const int sl = nb / s, mc = nb - sl * s;
   const int wa = lane >= sl ? 1 : 0, wb = lane > sl ? 1 : 0;
-  // the next filled entry (none yet: p_mx = 1 makes the first one found
-  // take NB(q+1) = p_pos = kWinOut)
-  int p_pos = kWinOut, p_lo = 0, p_mx = 1, p_nb = kWinOut;
+  // the next filled entry (none yet: a key no entry has makes the first
+  // one found take NB(q+1) = p_pos = kWinOut)
+  int p_pos = kWinOut, p_key = kWinNone, p_nb = kWinOut;
   int g = kWinInf;      // G of the next filled entry = D of the entries so far
   int last = -1;        // the lane's last filled entry
   int olo = kWinInf;    // lowest entry whose D is NB past the lane
@@ -1466,13 +1509,12 @@ __device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
     const int x = base + m;
     const int2 v = r[x];
     const bool fl = v.x <= v.y;
-    const bool mxb = GAP ? v.x < v.y : fl;
-    const int mx = mxb ? 1 : 0;
-    const int nq = (p_mx | mx | (p_lo ^ v.x)) ? p_pos : p_nb;
-    const int gq = mxb ? x : nq;
+    const bool mx = GAP ? v.x < v.y : fl;
+    const int key = mx ? x + kWinMix : v.x;
+    const int nq = key != p_key ? p_pos : p_nb;
+    const int gq = mx ? x : nq;
     p_pos = fl ? x : p_pos;
-    p_lo = fl ? v.x : p_lo;
-    p_mx = fl ? mx : p_mx;
+    p_key = fl ? key : p_key;
     p_nb = fl ? nq : p_nb;
     g = fl ? gq : g;
     last = max(last, fl ? x : -1);
@@ -1488,30 +1530,28 @@ __device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
   const int2 *ra = row - (idle ? base : wa * nb), *rb = row - (idle ? base : wb * nb);
   const int ka = wa ? 0 : k, kb = wb ? 0 : k;
   for (int m = s - 1; m >= mc; --m) step(m, ra, ka);
-  p_lo -= wa - wb;
+  if (p_key < kWinMix) p_key -= wa - wb;
   for (int m = mc - 1; m >= 0; --m) step(m, rb, kb);
-  p_lo -= wb;
+  if (p_key < kWinMix) p_key -= wb;
   // the lane's first filled entry is p (G(p) = g), its last one `last`
   const bool any = last >= 0;
-  int l_lo = 0, l_mx = 0;
+  int l_key = kWinNone;
   if (any) {
     // (an entry from L on, read from any bin, decides nothing)
     const int wrap = last >= nb ? 1 : 0;
     const int2 v = row[min(last - wrap * nb, nb - 1)];
-    l_lo = v.x - wrap;
-    l_mx = (GAP ? v.x < v.y : true) ? 1 : 0;
+    l_key = (GAP ? v.x < v.y : true) ? last + kWinMix : v.x - wrap;
   }
-  // the last filled entry of the lanes before: cycle number + 1, shifted,
-  // with the mixed flag in bit 0 (-1: none)
-  int xs = any ? (((l_lo + 1) << 1) | l_mx) : -1;
+  // the key of the last filled entry of the lanes before
+  int xs = l_key;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const int y = __shfl_up(xs, d, 64);
-    if (lane >= d && xs < 0) xs = y;
+    if (lane >= d && xs == kWinNone) xs = y;
   }
   int carry = __shfl_up(xs, 1, 64);
-  if (lane == 0) carry = -1;
-  const bool bf = any && (p_mx || (carry >= 0 && ((carry & 1) || (carry >> 1) - 1 != p_lo)));
+  if (lane == 0) carry = kWinNone;
+  const bool bf = any && (carry != kWinNone ? carry != p_key : p_key >= kWinMix);
   // the lane's first B: its first filled entry, or NB past it
   int nbx = bf ? p_pos : (any && p_nb != kWinOut ? p_nb : kWinInf);
 #pragma unroll
@@ -1582,18 +1622,19 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
       const double kr = __builtin_round(a.duration * f * nbd);
       s_f[tid] = f;
       s_k[tid] = kr < 1.0 ? 1 : kr > nbd ? nb : (int)kr;
+      if (wd.dmax * f >= (double)kMaxCycle) atomicOr(a.overflow, 1u);
     }
     for (int i = tid; i < np * nb; i += kBlock) s_mm[i] = make_int2(kCycleEmptyLo, kCycleEmptyHi);
     __syncthreads();
 
-    // Fold: cycle numbers per bin.
-    bool over = false;
+    // Fold: cycle numbers per bin (clamped at kMaxCycle, which the item's
+    // set-up has flagged: the largest d f of the cadence is its last kept
+    // time's).
     auto fold_point = [&](double d, double f, int2 *row) {
       const double cyc = d * f;
       const double e = floor(cyc);
       const int b = (int)min((unsigned)(int)(__builtin_amdgcn_fract(cyc) * nbd), nbm1);
-      over |= e >= (double)kMaxCycle;
-      const int ei = e >= (double)kMaxCycle ? kMaxCycle : (int)e;
+      const int ei = (int)fmin(e, (double)kMaxCycle);
       int *w2 = reinterpret_cast<int *>(row + b);
       atomicMin(w2, ei);
       atomicMax(w2 + 1, ei);
@@ -1626,7 +1667,6 @@ __global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
         }
       }
     }
-    if (over) atomicOr(a.overflow, 1u);
     __syncthreads();
 
     // Windows: one wave per period.

@@ -588,8 +588,9 @@ int enqueue_kernel(bls_plan *p, const PlannedBatch &pb, const double *periods, f
   sa.uws = pb.uws;
   sa.uws_stride = pb.uws_stride;
   sa.fold_policy = 0;
-  sa.pad_policy = 0;
+  sa.seed_unit = 1;
   if (const char *fm = getenv("BLS_FOLD_MERGE")) sa.fold_policy = atoi(fm) == 1 ? 1 : 2;
+  if (const char *su = getenv("BLS_SEED_UNIT")) sa.seed_unit = atoi(su) != 0 ? 1 : 0;
   sa.nparts = pb.nparts;
   sa.pad_parts = 0;
   for (int x = 0; x <= kMaxParts; ++x) sa.part_begin[x] = pb.part_begin[x];

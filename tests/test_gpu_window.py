@@ -168,6 +168,27 @@ def test_errors(bls, plan):
                                                         0.02, 2))
 
 
+def test_cycle_count_limit(bls, plan):
+    # cycle numbers are held below 2^29: a cadence whose last kept time lies
+    # more cycles than that after its first, at some trial period, is
+    # refused; just below the limit it is counted as usual
+    per = np.array([0.1, 1.0])
+    lim = float(1 << 29)
+    for span, ok in ((lim * 0.1 * 1.01, False), (lim * 1.0 * 0.99, True)):
+        t = np.array([10.0, 10.5, 11.0 + span * 0.5, 10.0 + span])
+        n_off = np.array([0, t.size], np.int64)
+        _say("window cycle limit", span, ok)
+        if ok:
+            g = _gpu(bls, plan, t, n_off, per[1:], None, 64, 0.02, 1)
+            assert np.array_equal(g, oracle.eclipse_window(t, None, per[1:],
+                                                           64, 0.02, 1))
+        else:
+            with pytest.raises(bls.BlsError) as ei:
+                _gpu(bls, plan, t, n_off, per, None, 64, 0.02, 1)
+            assert ei.value.status == bls.BLS_ERR_CAPACITY
+            assert "2^29" in bls.bls_last_error(plan)
+
+
 def test_full_size_sampled(bls, plan):
     """The efficiency workload at full size: 64 fields x 100000 periods,
     1000 trial epochs; every cadence checked on a sample of periods."""
