@@ -17,16 +17,10 @@
 //   unbinned_kernel box edges between points: per (curve, period) item the
 //                   phases ordered in LDS and every run of consecutive points
 //                   scored with exact sums
-//   detect_kernel   one workgroup per periodogram: SR statistics in one pass
-//                   and the strongest peaks with harmonic suppression, taken
-//                   from per-thread candidate lists
-//   window_prep_kernel / window_kernel  eclipse detection efficiency of a
-//                   cadence: per (cadence, period tile) the smallest and
-//                   largest cycle in each phase bin, then one decision per
-//                   trial eclipse epoch
-//   var_rms_kernel / var_clip_kernel  high-variability pre-search: per-star
-//                   RMS, then per (chip, magnitude bin) clipped statistics
-//                   and the flagged stars
+//
+// The detection statistics (bls_detect.hip), the eclipse detection
+// efficiency (bls_window.hip) and the high-variability pre-search
+// (bls_variability.hip) have sources of their own.
 //
 // No FP contraction anywhere (-ffp-contract=off): the phase is computed with
 // exactly the FP64 operation sequence of its definition so that every point
@@ -37,6 +31,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include "bls_block.h"
 #include "bls_device.h"
 #include "../../include/bls.h"
 
@@ -44,76 +39,6 @@ namespace bls {
 namespace {
 
 // ------------------------------------------------------------------ prep
-__device__ inline void block_sum2(double &a, double &b, double *sa, double *sb) {
-  const int tid = threadIdx.x;
-  sa[tid] = a;
-  sb[tid] = b;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      sa[tid] = sa[tid] + sa[tid + s];
-      sb[tid] = sb[tid] + sb[tid + s];
-    }
-    __syncthreads();
-  }
-  a = sa[0];
-  b = sb[0];
-  __syncthreads();
-}
-
-// Count, mean and sum of squared deviations of the workgroup's values from
-// each thread's own (n, mean, m2), merged pairwise in a fixed tree (the
-// update of Chan, Golub and LeVeque); threads without values hold n = 0.
-__device__ inline void block_chan(double &n, double &mean, double &m2, double *sa, double *sb,
-                                  double *sc) {
-  const int tid = threadIdx.x;
-  sa[tid] = n;
-  sb[tid] = mean;
-  sc[tid] = m2;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double na = sa[tid], nb = sa[tid + s];
-      if (nb > 0.0) {
-        if (na > 0.0) {
-          const double nn = na + nb;
-          const double delta = sb[tid + s] - sb[tid];
-          const double fb = nb / nn;
-          sb[tid] = sb[tid] + delta * fb;
-          sc[tid] = sc[tid] + sc[tid + s] + delta * delta * na * fb;
-          sa[tid] = nn;
-        } else {
-          sa[tid] = nb;
-          sb[tid] = sb[tid + s];
-          sc[tid] = sc[tid + s];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  n = sa[0];
-  mean = sb[0];
-  m2 = sc[0];
-  __syncthreads();
-}
-
-__device__ inline void block_minmax(double &mn, double &mx, double *sa, double *sb) {
-  const int tid = threadIdx.x;
-  sa[tid] = mn;
-  sb[tid] = mx;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      sa[tid] = fmin(sa[tid], sa[tid + s]);
-      sb[tid] = fmax(sb[tid], sb[tid + s]);
-    }
-    __syncthreads();
-  }
-  mn = sa[0];
-  mx = sb[0];
-  __syncthreads();
-}
-
 __device__ inline void block_isum2(long long &a, long long &b, long long *sa, long long *sb) {
   const int tid = threadIdx.x;
   sa[tid] = a;
@@ -1125,852 +1050,6 @@ __global__ void bins_kernel(const double *dt, int64_t n, const double *period, i
   }
 }
 
-// ------------------------------------------------------------- detection
-// One workgroup per curve: mean and population deviation of SR (FP64), then
-// peaks largest first, a peak at P suppressing every P' within
-// window * hP of hP for h in {1, 1/2, 2, 1/3, 3}.
-//
-// Peaks without a pass per peak: while the deviation pass reads SR, every
-// thread keeps the kDetList largest keys of its slice of periods (p = tid +
-// kBlock j, positive SR only) with their periods.  A key is (SR bits, ~p),
-// unique, and orders periods as the peaks are chosen (larger SR, then the
-// smaller index).  For each peak a thread offers its largest entry not yet
-// suppressed, the workgroup takes the largest offer, and every thread tests
-// its remaining entries against the new peak.  A thread whose entries are all
-// used up while its slice holds more positive values scans its slice again
-// against every peak so far and refills its list.
-// List length: each entry costs four VGPRs and insertion work in the
-// deviation pass; too short a list runs out near strong peaks and their
-// harmonics, and a refill re-reads the slice.  On 20000-period periodograms
-// of 2000-point curves, 12 is fastest for 8 peaks (8: refills set the
-// kernel's tail; 16: the pass loses occupancy).
-constexpr int kDetList = 12;
-constexpr int kDetBatch = 8;   // loads in flight per pass
-constexpr int kDetRefill = 4;  // loads in flight per refill (registers)
-
-__global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
-  __shared__ double sa[kBlock];
-  __shared__ double sb[kBlock];
-  __shared__ double sc[kBlock];
-  __shared__ unsigned long long s_key[kBlock / 64];  // one offer per wave
-  __shared__ double s_peak[BLS_MAX_PEAKS];
-  const int c = blockIdx.x;
-  if (c >= a.ncurves) return;
-  const DetectDesc dd = a.desc[c];
-  const int64_t m = dd.nperiods;
-  const float *sr = a.sr + dd.r_off;
-  const double *per = a.periods + dd.p_off;
-  bls_detection *out = reinterpret_cast<bls_detection *>(a.out) + c;
-  const int tid = threadIdx.x;
-
-  // One pass over SR.  A thread reads its slice kDetBatch values at a time
-  // (whole batches, then the tail) and keeps: the running count, mean and sum
-  // of squared deviations of its values, each batch merged in by the pairwise
-  // update of Chan, Golub and LeVeque (one value at a time in the tail); its
-  // largest value; and its list (descending keys).  The workgroup merges the
-  // threads' statistics the same way, in a fixed tree.
-  unsigned long long top[kDetList];
-#pragma unroll
-  for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
-  int npos = 0;  // positive SR values in this thread's slice
-  double cn = 0.0, cmean = 0.0, cm2 = 0.0, mx = -INFINITY;
-  auto take = [&](float v, int64_t p) {
-    mx = fmax(mx, (double)v);
-    if (v > 0.0f) {
-      ++npos;
-      unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                               (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-      if (key > top[kDetList - 1]) {
-#pragma unroll
-        for (int i = 0; i < kDetList; ++i) {
-          if (key > top[i]) {
-            const unsigned long long o = top[i];
-            top[i] = key;
-            key = o;
-          }
-        }
-      }
-    }
-  };
-  const int64_t full = m - (int64_t)(kDetBatch - 1) * kBlock;  // p0 < full: whole batch
-  int64_t p0 = tid;
-  for (; p0 < full; p0 += kDetBatch * kBlock) {
-    float v[kDetBatch];
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) v[u] = sr[p0 + (int64_t)u * kBlock];
-    double bs = 0.0;
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) bs = bs + (double)v[u];
-    const double bmean = bs * (1.0 / kDetBatch);  // exact: a power of two
-    double bm2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) {
-      const double dv = (double)v[u] - bmean;
-      bm2 = bm2 + dv * dv;
-    }
-    const double nn = cn + (double)kDetBatch;
-    const double delta = bmean - cmean;
-    const double fb = (double)kDetBatch / nn;
-    cmean = cmean + delta * fb;
-    cm2 = cm2 + bm2 + delta * delta * cn * fb;
-    cn = nn;
-#pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) take(v[u], p0 + (int64_t)u * kBlock);
-  }
-  for (int64_t p = p0; p < m; p += kBlock) {
-    const float v = sr[p];
-    cn = cn + 1.0;
-    const double delta = (double)v - cmean;
-    cmean = cmean + delta / cn;
-    cm2 = cm2 + delta * ((double)v - cmean);
-    take(v, p);
-  }
-  block_chan(cn, cmean, cm2, sa, sb, sc);
-  double mn = INFINITY;
-  block_minmax(mn, mx, sa, sb);
-  const double mean = cmean;
-  const double sd = sqrt(cm2 / (double)m);
-  const double sde = sd > 0.0 ? (mx - mean) / sd : 0.0;
-
-  auto key_index = [](unsigned long long key) -> int64_t {
-    return (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
-  };
-  double tper[kDetList];
-  unsigned dead = 0u;  // bit i: entry i empty, taken or suppressed
-#pragma unroll
-  for (int i = 0; i < kDetList; ++i) {
-    tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
-    if (!top[i]) dead |= 1u << i;
-  }
-  bool more = npos > kDetList;  // the slice holds values the list dropped
-  const double harm[5] = {1.0, 0.5, 2.0, 1.0 / 3.0, 3.0};
-  auto suppressed = [&](double Pp, double P) {
-    bool off = false;
-    for (int h = 0; h < 5; ++h) {
-      const double cp = harm[h] * P;
-      if (fabs(Pp - cp) <= a.window * cp) off = true;
-    }
-    return off;
-  };
-
-  int k = 0;
-  for (; k < a.max_peaks; ++k) {
-    if (dead == (1u << kDetList) - 1u && more) {
-      // Refill the list with the slice's largest entries free of every peak
-      // so far.  Only a value that would enter the list is tested; one that
-      // would not, or one pushed out, leaves `more` set (a later refill
-      // tests it then).
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
-      more = false;
-      auto retake = [&](float v, double Pp, int64_t p) {
-        if (!(v > 0.0f)) return;
-        unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                                 (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-        if (key < top[kDetList - 1]) {
-          more = true;
-          return;
-        }
-        bool off = false;
-        for (int j = 0; j < k; ++j) off = off || suppressed(Pp, s_peak[j]);
-        if (off) return;
-        if (top[kDetList - 1]) more = true;  // the last entry drops out
-#pragma unroll
-        for (int i = 0; i < kDetList; ++i) {
-          if (key > top[i]) {
-            const unsigned long long o = top[i];
-            top[i] = key;
-            key = o;
-          }
-        }
-      };
-      // Loads in batches, as in the passes above: a refill is a chain of
-      // dependent loads otherwise.
-      const int64_t rfull = m - (int64_t)(kDetRefill - 1) * kBlock;
-      int64_t q0 = tid;
-      for (; q0 < rfull; q0 += kDetRefill * kBlock) {
-        float v[kDetRefill];
-        double pp[kDetRefill];
-#pragma unroll
-        for (int u = 0; u < kDetRefill; ++u) {
-          v[u] = sr[q0 + (int64_t)u * kBlock];
-          pp[u] = per[q0 + (int64_t)u * kBlock];
-        }
-#pragma unroll
-        for (int u = 0; u < kDetRefill; ++u) retake(v[u], pp[u], q0 + (int64_t)u * kBlock);
-      }
-      for (int64_t q = q0; q < m; q += kBlock) retake(sr[q], per[q], q);
-      dead = 0u;
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i) {
-        tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
-        if (!top[i]) dead |= 1u << i;
-      }
-    }
-    unsigned long long offer = 0ull;
-    int mine = -1;
-#pragma unroll
-    for (int i = kDetList - 1; i >= 0; --i)
-      if (!((dead >> i) & 1u)) {
-        offer = top[i];
-        mine = i;
-      }
-    // Largest offer: across the wave by shuffles, across the waves in LDS.
-    // (Every read of s_key for the previous peak happened before the barrier
-    // that published that peak's period.)
-    unsigned long long wbest = offer;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long x = __shfl_xor(wbest, o);
-      wbest = x > wbest ? x : wbest;
-    }
-    if ((tid & 63) == 0) s_key[tid >> 6] = wbest;
-    __syncthreads();
-    unsigned long long key = s_key[0];
-#pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
-    if (key == 0ull) break;
-    if (offer == key) {  // the owner: its entry's period for everyone
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i)
-        if (i == mine) s_peak[k] = tper[i];
-    }
-    __syncthreads();
-    const double P = s_peak[k];
-    const int64_t pk = key_index(key);
-    const float vk = __uint_as_float((unsigned)(key >> 32));
-    if (tid == 0) {
-      out->peak_index[k] = pk;
-      out->peak_sr[k] = vk;
-      out->peak_sde[k] = sd > 0.0 ? (float)(((double)vk - mean) / sd) : 0.0f;
-    }
-    // The suppression test of every entry, harmonic by harmonic (the same
-    // products as the refill's test, so the two agree bit for bit).
-#pragma unroll
-    for (int h = 0; h < 5; ++h) {
-      const double cp = harm[h] * P;
-      const double wc = a.window * cp;
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i)
-        if (fabs(tper[i] - cp) <= wc) dead |= 1u << i;
-    }
-  }
-  if (tid == 0) {
-    out->mean_sr = mean;
-    out->std_sr = sd;
-    out->sde = sde;
-    out->npeaks = k;
-    out->candidate = sde >= a.threshold ? 1 : 0;
-    for (int i = k; i < BLS_MAX_PEAKS; ++i) {
-      out->peak_index[i] = -1;
-      out->peak_sr[i] = 0.0f;
-      out->peak_sde[i] = 0.0f;
-    }
-  }
-}
-
-// ------------------------------------------------------- eclipse window
-// Detection efficiency of a cadence.  Per trial period the kept times are
-// folded with the phase bins of the search (nphase bins); every bin keeps the
-// smallest and largest cycle number floor(d f) of the points in it.  The
-// eclipse starting at offset j covers bins j .. j+k-1 of one cycle, the
-// bins past the end of the cycle belonging to the eclipse one cycle earlier,
-// so over its window the eclipse numbers seen are cycle (bins >= j) and
-// cycle - 1 (wrapped bins); two distinct eclipses are observed exactly when
-// the largest such number exceeds the smallest, one when any bin is filled.
-
-__global__ __launch_bounds__(kBlock) void window_prep_kernel(WindowArgs a) {
-  __shared__ double sa[kBlock];
-  __shared__ double sb[kBlock];
-  const int c = blockIdx.x;
-  if (c >= a.ncurves) return;
-  WindowDesc *wd = a.desc + c;
-  const int64_t off = wd->n_off, n = wd->n;
-  const int tid = threadIdx.x;
-  double tmin = INFINITY, tmax = -INFINITY, bad = 0.0, kept = 0.0;
-  for (int64_t i = tid; i < n; i += kBlock) {
-    const double wi = a.w ? a.w[off + i] : 1.0;
-    if (!(wi >= 0.0) || isinf(wi)) {
-      bad = 1.0;
-      continue;
-    }
-    if (wi == 0.0) continue;
-    const double ti = a.t[off + i];
-    if (!isfinite(ti)) {
-      bad = 1.0;
-      continue;
-    }
-    kept = kept + 1.0;
-    tmin = fmin(tmin, ti);
-    tmax = fmax(tmax, ti);
-  }
-  double badp = 0.0;
-  if (wd->check_periods) {
-    for (int64_t i = tid; i < wd->nperiods; i += kBlock) {
-      const double P = a.periods[wd->p_off + i];
-      if (!isfinite(P) || !(P > 0.0)) badp = 1.0;
-    }
-  }
-  block_sum2(bad, kept, sa, sb);
-  double mx = badp;
-  block_minmax(tmin, mx, sa, sb);
-  double lo = INFINITY;
-  block_minmax(lo, tmax, sa, sb);
-  if (tid == 0) {
-    wd->t0 = tmin;
-    wd->dmax = tmax - tmin;
-    wd->status = bad > 0.0 ? kCurveBadData
-                 : kept < 1.0 ? kCurveTooFew
-                 : mx > 0.0 ? kCurveBadPeriod
-                            : kCurveOk;
-  }
-}
-
-constexpr int kCycleEmptyLo = 0x3fffffff;   // min of an empty bin
-constexpr int kCycleEmptyHi = -0x3fffffff;  // max of an empty bin
-
-// Integer wave sum through DPP moves (registers only): lanes exchange within
-// quads, half rows and rows, then rows are combined by row_bcast; lane 63
-// holds the total, which every lane receives.  Lanes a DPP step does not
-// write keep 0, so they add nothing.
-template <int CTRL, int ROWS>
-__device__ inline int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
-}
-
-__device__ inline int wave_isum(int v) {
-  v += dpp_i32<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v += dpp_i32<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v += dpp_i32<0x141, 0xf>(v);  // row_half_mirror
-  v += dpp_i32<0x140, 0xf>(v);  // row_mirror
-  v += dpp_i32<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_i32<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
-// The decision of every window of one period in one pass over its entries.
-// Entries are the nphase bins followed by the first k-1 bins again, one
-// cycle earlier (entry nb + b is bin b with its cycle numbers minus one), so
-// the window at offset j is the k entries j .. j+k-1 of E[0, L), L = nb+k-1.
-// A window holds two distinct eclipse numbers exactly when D(j) <= j+k-1,
-// where D(j) is the first entry at which its entries from j on hold two:
-//   NF(i)  first filled entry >= i;
-//   B(p)   filled p that is mixed (min < max), or whose previous filled
-//          entry is mixed or has another cycle number;
-//   NB(i)  first p >= i with B(p);
-//   G(f)   f if f is mixed, else NB(f+1) (the filled entries between are
-//          single-valued with f's number, and NB(f+1) is the first that is
-//          not);
-//   D(j) = G(NF(j)).
-// With one eclipse required every filled entry counts as mixed, and D(j) =
-// NF(j).  D(j) >= j, and no window reaches past L-1, so entries from L on
-// (read from any bin) decide nothing.
-//
-// One wave takes the period: lane l owns the s consecutive entries
-// [l s, l s + s), s odd so that the lanes' strided reads spread over the
-// LDS banks.  The lane walks its entries downwards keeping the next filled
-// entry p: at a filled entry q, B(p) follows from p and q alone (q is p's
-// previous filled entry), so NB(q+1) is p when B(p), else NB(p+1), and G(q)
-// follows.  Above the lane's last filled entry NB is NB past the lane,
-// carried as kWinOut until a wave scan supplies it.  Three wave scans join
-// the lanes: the last filled entry of the lanes before (for the B of the
-// lane's first filled entry), NB past the lane (a suffix minimum of the
-// lanes' first B), and the G of the first filled entry after the lane (for
-// the windows after its last filled entry).
-constexpr int kWinInf = 0x3fffffff;   // no such entry
-constexpr int kWinOut = 0x3ffffffe;   // NB past the lane, not yet known
-// A filled entry's key: its cycle number when single-valued, kWinMix + its
-// position when mixed, so that B(p) (seen from p's previous filled entry q)
-// is key(p) != key(q).  Cycle numbers are at most kMaxCycle < kWinMix.
-constexpr int kWinMix = 0x40000000;
-constexpr int kWinNone = -0x7fffffff;  // no filled entry
-
-template <int GAP>
-__device__ __forceinline__ int window_period(const int2 *row, int nb, int k) {
-  const int lane = threadIdx.x & 63;
-  const int L = nb + k - 1;
-  const int s = ((L + 63) >> 6) | 1;
-  const int base = lane * s;
-  // Lane nb / s holds entry nb at offset nb % s: above that offset the
-  // lanes from it on hold wrapped entries, below it those after it.  Within
-  // each part a lane's entries are all wrapped or none are, so cycle numbers
-  // are compared as stored and the next filled entry's number is moved into
-  // the unwrapped frame where the lane crosses.
-  const int sl = nb / s, mc = nb - sl * s;
-  const int wa = lane >= sl ? 1 : 0, wb = lane > sl ? 1 : 0;
-  // the next filled entry (none yet: a key no entry has makes the first
-  // one found take NB(q+1) = p_pos = kWinOut)
-  int p_pos = kWinOut, p_key = kWinNone, p_nb = kWinOut;
-  int g = kWinInf;      // G of the next filled entry = D of the entries so far
-  int last = -1;        // the lane's last filled entry
-  int olo = kWinInf;    // lowest entry whose D is NB past the lane
-  int cnt = 0;
-  auto step = [&](int m, const int2 *r, int kk) {
-    const int x = base + m;
-    const int2 v = r[x];
-    const bool fl = v.x <= v.y;
-    const bool mx = GAP ? v.x < v.y : fl;
-    const int key = mx ? x + kWinMix : v.x;
-    const int nq = key != p_key ? p_pos : p_nb;
-    const int gq = mx ? x : nq;
-    p_pos = fl ? x : p_pos;
-    p_key = fl ? key : p_key;
-    p_nb = fl ? nq : p_nb;
-    g = fl ? gq : g;
-    last = max(last, fl ? x : -1);
-    olo = g == kWinOut ? x : olo;
-    cnt += g < x + kk ? 1 : 0;
-  };
-  // wrapped entries x read bin x - nb; entries from L on decide nothing:
-  // a lane holding only such entries reads the first s bins, the lane
-  // holding entry L reads up to s - 2 entries past the period's wrapped
-  // copy (into the next period or the workspace's padding).  Only unwrapped
-  // entries start windows.
-  const bool idle = base >= L;
-  const int2 *ra = row - (idle ? base : wa * nb), *rb = row - (idle ? base : wb * nb);
-  const int ka = wa ? 0 : k, kb = wb ? 0 : k;
-  for (int m = s - 1; m >= mc; --m) step(m, ra, ka);
-  if (p_key < kWinMix) p_key -= wa - wb;
-  for (int m = mc - 1; m >= 0; --m) step(m, rb, kb);
-  if (p_key < kWinMix) p_key -= wb;
-  // the lane's first filled entry is p (G(p) = g), its last one `last`
-  const bool any = last >= 0;
-  int l_key = kWinNone;
-  if (any) {
-    // (an entry from L on, read from any bin, decides nothing)
-    const int wrap = last >= nb ? 1 : 0;
-    const int2 v = row[min(last - wrap * nb, nb - 1)];
-    l_key = (GAP ? v.x < v.y : true) ? last + kWinMix : v.x - wrap;
-  }
-  // the key of the last filled entry of the lanes before
-  int xs = l_key;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(xs, d, 64);
-    if (lane >= d && xs == kWinNone) xs = y;
-  }
-  int carry = __shfl_up(xs, 1, 64);
-  if (lane == 0) carry = kWinNone;
-  const bool bf = any && (carry != kWinNone ? carry != p_key : p_key >= kWinMix);
-  // the lane's first B: its first filled entry, or NB past it
-  int nbx = bf ? p_pos : (any && p_nb != kWinOut ? p_nb : kWinInf);
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_down(nbx, d, 64);
-    if (lane + d < 64) nbx = min(nbx, y);
-  }
-  int nb_out = __shfl_down(nbx, 1, 64);
-  if (lane == 63) nb_out = kWinInf;
-  // entries olo .. last have D = NB past the lane
-  if (any && olo <= last && nb_out < kWinInf)
-    cnt += max(0, min(last + 1, nb) - max(olo, nb_out - k + 1));
-  // the entries after the last filled one have D = G of the next filled
-  // entry of the lanes after
-  int gx = any ? (g == kWinOut ? nb_out : g) : -1;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_down(gx, d, 64);
-    if (lane + d < 64 && gx < 0) gx = y;
-  }
-  int gc = __shfl_down(gx, 1, 64);
-  if (lane == 63) gc = -1;
-  if (gc >= 0 && gc < kWinInf)
-    cnt += max(0, min(base + s, nb) - max(max(last + 1, base), gc - k + 1));
-  return wave_isum(cnt);
-}
-
-template <int GAP>
-__global__ __launch_bounds__(kBlock) void window_kernel(WindowArgs a) {
-  extern __shared__ int2 s_mm[];            // [tile][nphase] (min, max cycle), padding
-  __shared__ double s_f[kTileMax];
-  __shared__ int s_k[kTileMax];
-  static_assert(sizeof(s_f) + sizeof(s_k) == kWindowStaticLds, "window kernel static LDS");
-  const int tid = threadIdx.x;
-  const int nb = a.nphase;
-  const double nbd = (double)nb;
-  const unsigned nbm1 = (unsigned)(nb - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-  // A workgroup's items increase, so its cadence only moves forward: keep
-  // the current one and the first item of the next.
-  int cur = 0;
-  int64_t next0 = a.ncurves > 1 ? a.desc[1].item0 : a.nitems;
-  WindowDesc wd = a.desc[0];
-  // The cadence's times (d = t - t0, kept points only) stay in registers
-  // across the workgroup's items of that cadence when it has at most
-  // kBlock * kWinRegs points; longer cadences are read again per item.
-  constexpr int kWinRegs = 8;
-  double dreg[kWinRegs];
-  bool kreg[kWinRegs];
-  int cached = -1;
-  for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-    if (item >= next0) {
-      while (cur + 1 < a.ncurves && a.desc[cur + 1].item0 <= item) ++cur;
-      wd = a.desc[cur];
-      next0 = cur + 1 < a.ncurves ? a.desc[cur + 1].item0 : a.nitems;
-    }
-    const int p0 = (int)(item - wd.item0) * a.tile;
-    const int np = min(a.tile, wd.nperiods - p0);
-    int32_t *out = a.observed + wd.r_off + p0;
-    // One barrier sequence for every item: invalid cadences fall through to
-    // the barrier at the end of the loop body rather than `continue`.
-    if (wd.status != kCurveOk) {
-      if (tid < np) out[tid] = -1;
-    } else {
-    if (tid < np) {
-      const double f = 1.0 / a.periods[wd.p_off + p0 + tid];
-      const double kr = __builtin_round(a.duration * f * nbd);
-      s_f[tid] = f;
-      s_k[tid] = kr < 1.0 ? 1 : kr > nbd ? nb : (int)kr;
-      if (wd.dmax * f >= (double)kMaxCycle) atomicOr(a.overflow, 1u);
-    }
-    for (int i = tid; i < np * nb; i += kBlock) s_mm[i] = make_int2(kCycleEmptyLo, kCycleEmptyHi);
-    __syncthreads();
-
-    // Fold: cycle numbers per bin (clamped at kMaxCycle, which the item's
-    // set-up has flagged: the largest d f of the cadence is its last kept
-    // time's).
-    auto fold_point = [&](double d, double f, int2 *row) {
-      const double cyc = d * f;
-      const double e = floor(cyc);
-      const int b = (int)min((unsigned)(int)(__builtin_amdgcn_fract(cyc) * nbd), nbm1);
-      const int ei = (int)fmin(e, (double)kMaxCycle);
-      int *w2 = reinterpret_cast<int *>(row + b);
-      atomicMin(w2, ei);
-      atomicMax(w2 + 1, ei);
-    };
-    if (wd.n <= (int64_t)kBlock * kWinRegs) {
-      if (cached != cur) {
-#pragma unroll
-        for (int r = 0; r < kWinRegs; ++r) {
-          const int64_t i = tid + (int64_t)kBlock * r;
-          const bool in = i < wd.n;
-          const double wi = in ? (a.w ? a.w[wd.n_off + i] : 1.0) : 0.0;
-          kreg[r] = in && wi != 0.0;
-          dreg[r] = kreg[r] ? a.t[wd.n_off + i] - wd.t0 : 0.0;
-        }
-        cached = cur;
-      }
-      for (int t = 0; t < np; ++t) {
-        const double f = s_f[t];
-#pragma unroll
-        for (int r = 0; r < kWinRegs; ++r)
-          if (kreg[r]) fold_point(dreg[r], f, s_mm + t * nb);
-      }
-    } else {
-      for (int t = 0; t < np; ++t) {
-        const double f = s_f[t];
-        for (int64_t i = tid; i < wd.n; i += kBlock) {
-          const double wi = a.w ? a.w[wd.n_off + i] : 1.0;
-          if (wi == 0.0) continue;
-          fold_point(a.t[wd.n_off + i] - wd.t0, f, s_mm + t * nb);
-        }
-      }
-    }
-    __syncthreads();
-
-    // Windows: one wave per period.
-    for (int t = wave; t < np; t += kBlock / 64) {
-      const int k = __builtin_amdgcn_readfirstlane(s_k[t]);
-      const int c = window_period<GAP>(s_mm + t * nb, nb, k);
-      if ((tid & 63) == 0) out[t] = c;
-    }
-    }  // valid cadence
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------- variability pre-search
-// Stability of every star (population RMS of its kept values) and its
-// magnitude bin, then per (chip, bin) an iterated sigma-clipped mean and
-// deviation and the stars above it by flag_sigma deviations.  All sums run
-// in FP64 in a fixed lane order combined by a fixed butterfly, so results do
-// not depend on scheduling.
-
-// Wave sums in a fixed order, through DPP moves (registers only, no LDS
-// round trip per step): lanes exchange within quads, then half rows and rows
-// of 16 (every lane then holds its row's sum), then row 0 is added into row
-// 1 and row 2 into row 3 (row_bcast:15), then rows 0-1 into rows 2-3
-// (row_bcast:31); lane 63 holds the total, which is read out to every lane.
-// Lanes a DPP step does not write keep 0, so they add nothing.
-
-template <int CTRL, int ROWS>
-__device__ inline double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_i32<CTRL, ROWS>((int)(unsigned)(b & 0xffffffffll));
-  const int hi = dpp_i32<CTRL, ROWS>((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ inline double wave_sum(double v) {
-  v = v + dpp_f64<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  v = v + dpp_f64<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  v = v + dpp_f64<0x141, 0xf>(v);  // row_half_mirror
-  v = v + dpp_f64<0x140, 0xf>(v);  // row_mirror
-  v = v + dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v = v + dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-
-// Sums over each half of a wave (lanes 0-31 and 32-63) in a fixed order:
-// the steps of wave_sum up to row_bcast:15, which leave the halves' totals
-// in lanes 31 and 63; every lane receives its own half's total.
-__device__ inline double half_sum(double v) {
-  v = v + dpp_f64<0xb1, 0xf>(v);
-  v = v + dpp_f64<0x4e, 0xf>(v);
-  v = v + dpp_f64<0x141, 0xf>(v);
-  v = v + dpp_f64<0x140, 0xf>(v);
-  v = v + dpp_f64<0x142, 0xa>(v);
-  const long long b = __double_as_longlong(v);
-  const int lo0 = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 31);
-  const int hi0 = __builtin_amdgcn_readlane((int)(b >> 32), 31);
-  const int lo1 = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
-  const int hi1 = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  const bool upper = (threadIdx.x & 32) != 0;
-  const int lo = upper ? lo1 : lo0, hi = upper ? hi1 : hi0;
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ inline int half_isum(int v) {
-  v += dpp_i32<0xb1, 0xf>(v);
-  v += dpp_i32<0x4e, 0xf>(v);
-  v += dpp_i32<0x141, 0xf>(v);
-  v += dpp_i32<0x140, 0xf>(v);
-  v += dpp_i32<0x142, 0xa>(v);
-  const int t0 = __builtin_amdgcn_readlane(v, 31), t1 = __builtin_amdgcn_readlane(v, 63);
-  return (threadIdx.x & 32) ? t1 : t0;
-}
-
-// Half a wave per star (two stars per wave, so half as many waves wait on
-// memory): the mean, then the mean squared deviation (two passes, as the
-// definition reads).  A star of up to 320 values is loaded once into
-// registers (10 per lane, all loads in flight together) and both passes run
-// there; longer stars take the second pass from memory again.  Every lane
-// stays active through the sums: a half past the last star works on an
-// empty one and writes nothing.
-constexpr int kVarLanes = 32;
-constexpr int kVarRegs = 10;
-
-__global__ __launch_bounds__(kBlock) void var_rms_kernel(VarArgs a) {
-  const int lane = threadIdx.x & (kVarLanes - 1);
-  const int c = blockIdx.x * (kBlock / kVarLanes) + (threadIdx.x / kVarLanes);
-  const bool live = c < a.ncurves;
-  // The star's offsets and magnitude are loaded together up front (one
-  // round trip before the values, none after them).
-  const int64_t off = live ? a.n_off[c] : 0;
-  const int64_t n = live ? a.n_off[c + 1] - off : 0;
-  const double mag = live ? a.mag[c] : 0.0;
-  const double *x = a.x + off;
-  const double *w = a.w ? a.w + off : nullptr;
-  int cnt = 0, bad = 0;
-  double s = 0.0;
-  double xv[kVarRegs];
-  bool kv[kVarRegs];
-#pragma unroll
-  for (int u = 0; u < kVarRegs; ++u) {   // lanes past the end keep nothing
-    xv[u] = 0.0;
-    kv[u] = false;
-  }
-  for (int64_t i0 = lane; i0 < n; i0 += kVarLanes * kVarRegs) {
-#pragma unroll
-    for (int u = 0; u < kVarRegs; ++u) {
-      const int64_t i = i0 + kVarLanes * u;
-      xv[u] = i < n ? x[i] : 0.0;
-      const double wi = i < n ? (w ? w[i] : 1.0) : 0.0;
-      if (!(wi >= 0.0) || isinf(wi)) bad = 1;
-      kv[u] = wi > 0.0 && !isinf(wi);
-    }
-#pragma unroll
-    for (int u = 0; u < kVarRegs; ++u) {
-      if (!kv[u]) continue;
-      if (!isfinite(xv[u])) bad = 1;
-      s = s + xv[u];
-      ++cnt;
-    }
-  }
-  s = half_sum(s);
-  cnt = half_isum(cnt);
-  bad = half_isum(bad);
-  const double mu = s / (double)cnt;
-  double ss = 0.0;
-  if (!bad && cnt > 0) {
-    if (n <= kVarLanes * kVarRegs) {
-#pragma unroll
-      for (int u = 0; u < kVarRegs; ++u) {
-        if (!kv[u]) continue;
-        const double dv = xv[u] - mu;
-        ss = ss + dv * dv;
-      }
-    } else {
-      for (int64_t i = lane; i < n; i += kVarLanes) {
-        const double wi = w ? w[i] : 1.0;
-        if (wi == 0.0) continue;
-        const double dv = x[i] - mu;
-        ss = ss + dv * dv;
-      }
-    }
-  }
-  ss = half_sum(ss);
-  if (lane != 0 || !live) return;
-  if (bad || cnt == 0) {
-    a.rms[c] = __longlong_as_double(0x7ff8000000000000ll);
-    a.bin[c] = -1;
-    a.flag[c] = -1;
-    return;
-  }
-  a.rms[c] = sqrt(ss / (double)cnt);
-  a.flag[c] = 0;
-  int b = -1;
-  if (isfinite(mag)) {
-    const double q = floor((mag - a.origin) / a.width);
-    if (q >= 0.0 && q < (double)a.nmagbins) b = (int)q;
-  }
-  a.bin[c] = b;
-}
-
-constexpr int kVarRegionCap = 1024;  // members one wave keeps in LDS
-
-// Sum over the workgroup in a fixed order: wave butterflies, then the four
-// wave totals in wave order; every thread receives the same value.
-__device__ inline double block_sum_fixed(double v, double *s_red) {
-  v = wave_sum(v);
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) s_red[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int w = 0; w < kBlock / 64; ++w) t = t + s_red[w];
-  __syncthreads();
-  return t;
-}
-
-// One workgroup per (chip, bin).  Each wave scans a quarter of the chip's
-// stars and keeps its members in its own LDS region, so the regions in wave
-// order list the members in star order; a wave with more members than its
-// region holds sends the whole task to rescanning the chip instead.
-__global__ __launch_bounds__(kBlock) void var_clip_kernel(VarArgs a) {
-  __shared__ int s_list[kBlock / 64][kVarRegionCap];
-  __shared__ double s_val[kBlock / 64][kVarRegionCap];     // members' RMS
-  __shared__ unsigned char s_alive[kBlock / 64][kVarRegionCap];
-  __shared__ int s_wcnt[kBlock / 64];
-  __shared__ double s_red[kBlock / 64];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int64_t task = blockIdx.x;
-  if (task >= (int64_t)a.nchips * a.nmagbins) return;
-  const int k = (int)(task / a.nmagbins);
-  const int b = (int)(task - (int64_t)k * a.nmagbins);
-  const int c0 = (int)a.chip_off[k], c1 = (int)a.chip_off[k + 1];
-  const int quarter = (c1 - c0 + 3) / 4;
-  const int w0 = min(c1, c0 + wv * quarter), w1 = min(c1, w0 + quarter);
-
-  // Members of this wave's quarter, in star order, all alive; eight chunks
-  // of bin numbers are loaded together per round.
-  int cnt_w = 0;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  for (int base = w0; base < w1; base += 64 * 8) {
-    int bv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int st = base + 64 * u + lane;
-      bv[u] = st < w1 ? a.bin[st] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int st = base + 64 * u + lane;
-      const bool mem = bv[u] == b;
-      const unsigned long long mask = __ballot(mem);
-      if (mem) {
-        const int pos = cnt_w + __popcll(mask & below);
-        if (pos < kVarRegionCap) s_list[wv][pos] = st;
-        a.alive[st] = 1;
-      }
-      cnt_w += __popcll(mask);
-    }
-  }
-  if (lane == 0) s_wcnt[wv] = cnt_w;
-  __syncthreads();
-  int cnt0 = 0;
-  bool fits = true;
-  for (int w = 0; w < kBlock / 64; ++w) {
-    cnt0 += s_wcnt[w];
-    fits = fits && s_wcnt[w] <= kVarRegionCap;
-  }
-  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
-  if (cnt0 == 0) {
-    if (tid == 0) {
-      a.bin_mean[task] = qnan;
-      a.bin_std[task] = qnan;
-      a.bin_count[task] = 0;
-    }
-    return;  // uniform: every thread saw cnt0 == 0
-  }
-  // Visit the members in star order: the regions in wave order (value and
-  // alive flag in LDS, gathered once), or a rescan of the chip when a region
-  // overflowed.  f(value, alive flag, star).
-  if (fits) {
-    for (int w = 0; w < kBlock / 64; ++w)
-      for (int i = tid; i < s_wcnt[w]; i += kBlock) {
-        s_val[w][i] = a.rms[s_list[w][i]];
-        s_alive[w][i] = 1;
-      }
-    __syncthreads();
-  }
-  auto for_members = [&](auto f) {
-    if (fits) {
-      for (int w = 0; w < kBlock / 64; ++w)
-        for (int i = tid; i < s_wcnt[w]; i += kBlock)
-          f(s_val[w][i], s_alive[w][i], s_list[w][i]);
-    } else {
-      for (int st = c0 + tid; st < c1; st += kBlock)
-        if (a.bin[st] == b) f(a.rms[st], a.alive[st], st);
-    }
-  };
-  int cnt = cnt0;
-  double mu = 0.0, sd = 0.0;
-  for (int it = 0;; ++it) {
-    double sum = 0.0;
-    for_members([&](double v, unsigned char &alive, int) {
-      if (alive) sum = sum + v;
-    });
-    mu = block_sum_fixed(sum, s_red) / (double)cnt;
-    double ss = 0.0;
-    for_members([&](double v, unsigned char &alive, int) {
-      if (alive) {
-        const double dv = v - mu;
-        ss = ss + dv * dv;
-      }
-    });
-    sd = sqrt(block_sum_fixed(ss, s_red) / (double)cnt);
-    if (it >= a.max_iter) break;
-    const double lo = mu - a.clip_sigma * sd, hi = mu + a.clip_sigma * sd;
-    double drop = 0.0;
-    for_members([&](double v, unsigned char &alive, int) {
-      if (alive && !(v >= lo && v <= hi)) {
-        alive = 0;
-        drop = drop + 1.0;
-      }
-    });
-    const int dropped = (int)block_sum_fixed(drop, s_red);
-    if (dropped == 0) break;
-    cnt -= dropped;
-  }
-  if (tid == 0) {
-    a.bin_mean[task] = mu;
-    a.bin_std[task] = sd;
-    a.bin_count[task] = cnt;
-  }
-  if (cnt < a.min_stars) return;
-  const double thr = mu + a.flag_sigma * sd;
-  for_members([&](double v, unsigned char &, int st) {
-    if (v > thr) a.flag[st] = 1;
-  });
-}
-
 // ------------------------------------------------------ unbinned search
 // Box edges between data points: per period the kept points are put in
 // phase order (ties by index) and every cyclic run that some box with duty
@@ -2364,53 +1443,11 @@ int launch_bins(const double *dt, int64_t n, const double *period, int32_t nbins
   return (int)hipGetLastError();
 }
 
-int launch_detect(const DetectArgs &a, void *stream) {
-  if (a.ncurves <= 0) return 0;
-  hipLaunchKernelGGL(detect_kernel, dim3(a.ncurves), dim3(kBlock), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
-}
-
 int launch_best_index(unsigned long long *keys, int32_t n, void *stream) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(best_index_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                      keys, n);
   return (int)hipGetLastError();
-}
-
-int launch_window(const WindowArgs &a, int grid, void *stream) {
-  if (a.ncurves <= 0) return 0;
-  hipLaunchKernelGGL(window_prep_kernel, dim3(a.ncurves), dim3(kBlock), 0, (hipStream_t)stream,
-                     a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.nitems <= 0) return (int)e;
-  const int lds = window_lds_bytes(a.tile, a.nphase);
-  const void *fn = a.min_eclipses >= 2 ? reinterpret_cast<const void *>(&window_kernel<1>)
-                                       : reinterpret_cast<const void *>(&window_kernel<0>);
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return (int)e;
-  void *args[] = {const_cast<WindowArgs *>(&a)};
-  e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)lds, (hipStream_t)stream);
-  if (e != hipSuccess) return (int)e;
-  return (int)hipGetLastError();
-}
-
-int launch_variability(const VarArgs &a, void *stream) {
-  if (a.ncurves <= 0 || a.nchips <= 0) return 0;
-  hipStream_t s = (hipStream_t)stream;
-  const int per = kBlock / kVarLanes;
-  hipLaunchKernelGGL(var_rms_kernel, dim3((a.ncurves + per - 1) / per), dim3(kBlock), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return (int)e;
-  const int64_t tasks = (int64_t)a.nchips * a.nmagbins;
-  hipLaunchKernelGGL(var_clip_kernel, dim3((unsigned)tasks), dim3(kBlock), 0, s, a);
-  return (int)hipGetLastError();
-}
-
-int window_blocks_per_cu(int lds_bytes, int *blocks) {
-  const void *fn = reinterpret_cast<const void *>(&window_kernel<1>);
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  if (e != hipSuccess) return (int)e;
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
 }
 
 int64_t unbinned_lds_bytes(int n, bool weighted) {
