@@ -267,14 +267,16 @@ __device__ inline int fold_lane_gap(double fmin, int nbins, float cadence) {
 }
 
 // Whether a tile's fold merges a thread's consecutive same-bin points: when
-// one cadence step advances the phase by less than a bin at the tile's
-// longest period (frequency fmin), unless the launch fixes the choice
-// (policy 1: always, 2: never).  Any answer is correct; this one only picks
-// the faster fold.
+// one cadence step advances the phase by less than 0.3 bins at the tile's
+// longest period (frequency fmin), so that runs of about three points or
+// more share a bin, unless the launch fixes the choice (policy 1: always,
+// 2: never).  The merge costs VALU operations on every point and saves one
+// LDS atomic per point it joins; shorter runs do not repay it.  Any answer
+// is correct; this one only picks the faster fold.
 __device__ inline bool fold_merges(double fmin, int nbins, float cadence, int policy) {
   if (policy != 0) return policy == 1;
   const double x = fmin * (double)nbins * (double)cadence;
-  return !(x >= 1.0);
+  return !(x >= 0.3);
 }
 
 // Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
