@@ -271,12 +271,14 @@ __device__ inline int fold_lane_gap(double fmin, int nbins, float cadence) {
 // longest period (frequency fmin), so that runs of about three points or
 // more share a bin, unless the launch fixes the choice (policy 1: always,
 // 2: never).  The merge costs VALU operations on every point and saves one
-// LDS atomic per point it joins; shorter runs do not repay it.  Any answer
-// is correct; this one only picks the faster fold.
-__device__ inline bool fold_merges(double fmin, int nbins, float cadence, int policy) {
+// LDS atomic per point it joins; shorter runs do not repay it.  A weighted
+// point saves two atomics, and there the merge pays from one bin per step.
+// Any answer is correct; this one only picks the faster fold.
+__device__ inline bool fold_merges(double fmin, int nbins, float cadence, int policy,
+                                   bool weighted) {
   if (policy != 0) return policy == 1;
   const double x = fmin * (double)nbins * (double)cadence;
-  return !(x >= 0.3);
+  return !(x >= (weighted ? 1.0 : 0.3));
 }
 
 // Fold and bin one chunk of kBlock * kPPT points into the tile's histograms.
@@ -828,7 +830,7 @@ void search_kernel(SearchArgs a) {
         __builtin_amdgcn_readfirstlane(fold_lane_gap(ftile, cd.nbins, cd.cadence));
     // Merging a thread's same-bin points pays only where one cadence step
     // moves the phase by less than a bin at the tile's longest period.
-    const bool merge = fold_merges(ftile, cd.nbins, cd.cadence, a.fold_policy);
+    const bool merge = fold_merges(ftile, cd.nbins, cd.cadence, a.fold_policy, WEIGHTED);
 
     // Fold and bin: points in registers, reused for every period of the tile.
     for (int64_t base = 0; base < cd.n; base += (int64_t)kBlock * kPPT) {
