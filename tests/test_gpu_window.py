@@ -103,6 +103,25 @@ def test_dense_and_sparse_cadences(bls, plan, nphase, dur, m):
         assert np.array_equal(gc, o), (c, np.flatnonzero(gc != o)[:5])
 
 
+@pytest.mark.parametrize("nphase,m", [(1000, 2), (1000, 1), (257, 2), (64, 2)])
+def test_one_cycle_and_a_little(bls, plan, nphase, m):
+    # a cadence just over one cycle at most trial periods: nearly every bin
+    # holds one cycle number, the same one, so each window's decision hangs
+    # on the few bins of the second cycle, far from most offsets (long runs
+    # of single-valued entries across many lanes of the window pass)
+    ts = [synth.T_START + np.linspace(0.0, 1.3, 500),
+          synth.T_START + np.sort(np.random.default_rng(3).uniform(0, 2.05, 300))]
+    t, n_off = _pack(ts)
+    per = np.linspace(0.6, 2.2, 161)
+    _say("window one cycle and a little", nphase, m)
+    g = _gpu(bls, plan, t, n_off, per, None, nphase, 0.07, m)
+    for c, tc in enumerate(ts):
+        o = oracle.eclipse_window(tc, None, per, nphase, 0.07, m)
+        gc = g[c * per.size:(c + 1) * per.size]
+        assert np.array_equal(gc, o), (c, np.flatnonzero(gc != o)[:5])
+    assert g.max() > 0 and g.min() < nphase
+
+
 def test_per_cadence_grids_and_zero_weights(bls, plan):
     ts = _cadences(301, 7)
     t, n_off = _pack(ts)
