@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbls_mi355x.so")
 
-SOURCES = ["bls_kernels.hip", "bls_detect.hip", "bls_window.hip",
+SOURCES = ["bls_kernels.hip", "bls_unbinned.hip", "bls_detect.hip", "bls_window.hip",
            "bls_variability.hip", "bls_plan.cpp", "bls_autotune.cpp",
            "bls_server.cpp", "bls_noalloc.hip", "bls_recovery.hip"]
 

@@ -1,0 +1,355 @@
+// gfx950 kernel of the unbinned box search (box edges between data points,
+// a range of durations and phases taken to the data, section 2.2.2).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "bls_device.h"
+#include "bls_items.h"
+#include "../../include/bls.h"
+
+namespace bls {
+namespace {
+
+// ------------------------------------------------------ unbinned search
+// Box edges between data points: per period the kept points are put in
+// phase order (ties by index) and every cyclic run that some box with duty
+// cycle in [qlo, qhi] holds exactly is scored.  The order is found without a
+// comparison sort: a counting sort on a fine phase grid (about one point per
+// cell) groups the points, and each point's rank is its cell's start plus
+// the number of cell mates that precede it.  Sums over a run are exact:
+// FP64 sums of the integer fixed-point values of the prep pass, below 2^53.
+
+__host__ __device__ inline int pow2_at_least(int n) {
+  int m = 1;
+  while (m < n) m <<= 1;
+  return m;
+}
+
+// Forward phase distance from sorted position i (phase pi) to j (phase pj),
+// one cycle added when the step passes the end of the order.
+__device__ inline double fwd_phase(double pi, double pj, int i, int j) {
+  return j > i ? pj - pi : (pj + 1.0) - pi;
+}
+
+// GLOB: the per-point arrays live in the workgroup's slice of a device
+// workspace instead of LDS (curves longer than LDS holds); the steps are the
+// same, only slower.
+template <bool WEIGHTED, bool DIP, bool GLOB>
+__global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) unsigned char s_lds[];
+  __shared__ long long s_item;
+  __shared__ int s_curve;
+  __shared__ int s_per;
+  __shared__ unsigned long long s_vbits;
+  __shared__ unsigned long long s_theta;
+  __shared__ unsigned int s_tie;
+  __shared__ long long s_bestS, s_bestR;
+  __shared__ long long s_wsum[kBlock / 64];
+  __shared__ int s_part[kBlock];
+
+  const int tid = threadIdx.x;
+  const int N = a.ucap;
+  const int Mc = pow2_at_least(N);
+  unsigned char *s_raw = GLOB ? a.uws + (int64_t)blockIdx.x * a.uws_stride : s_lds;
+  double *ph_u = reinterpret_cast<double *>(s_raw);
+  double *sph = ph_u + N;
+  int *sq = reinterpret_cast<int *>(sph + N);
+  int *sidx = sq + N;
+  int *grp = sidx + N;
+  int *cnt = grp + N;
+  int *sw = cnt + Mc + 1;   // weighted only
+
+  unsigned done_mask = 0u;
+  SegCache sc = {0, 0, 0, 0};
+  ItemRef nx = {-1, 0, 0};
+  if (tid == 0) nx = claim_item(a, done_mask, sc);  // one item ahead
+  for (;;) {
+    if (tid == 0) {
+      s_item = nx.item;
+      s_curve = nx.curve;
+      s_per = nx.tile;
+    }
+    __syncthreads();
+    if (s_item < 0) break;
+    const int c = __builtin_amdgcn_readfirstlane(s_curve);
+    const int p = __builtin_amdgcn_readfirstlane(s_per);
+    __syncthreads();
+    if (tid == 0) nx = claim_item(a, done_mask, sc);
+
+    const CurveDesc cd = a.curves[c];
+    const int64_t r_out = cd.r_off + p;
+    // Every item, valid or not, reaches the one barrier at the end of the
+    // loop body: a `continue` here would give the loop header a second way
+    // in that skips thread 0's fetch, and the compiler may then keep the
+    // other lanes circling the header barrier without thread 0.
+    if (cd.status != kCurveOk) {
+      if (tid == 0) {
+        a.sr[r_out] = NAN;
+        a.depth[r_out] = NAN;
+        a.jstart[r_out] = -1;
+        a.kwidth[r_out] = -1;
+      }
+    } else {
+    const int n = (int)cd.n;
+    const int M = pow2_at_least(n);
+    const double Md = (double)M;
+    const double f = 1.0 / a.periods[cd.p_off + p];
+    const double *dt = a.dt + cd.n_off;
+    const int32_t *q = a.q + cd.n_off;
+    const int32_t *qw = WEIGHTED ? a.qw + cd.n_off : nullptr;
+
+    // Phases and fine-grid cells; dropped points go to the extra cell M.
+    for (int i = tid; i <= M; i += kBlock) cnt[i] = 0;
+    if (tid == 0) {
+      s_vbits = 0ull;
+      s_theta = 0ull;
+      s_tie = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    long long wsum = 0;
+    for (int i = tid; i < n; i += kBlock) {
+      const bool kept = WEIGHTED ? qw[i] >= 0 : true;
+      const double ph = __builtin_amdgcn_fract(dt[i] * f);
+      ph_u[i] = kept ? ph : 2.0;
+      const int cell = kept ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      atomicAdd(&cnt[cell], 1);
+      if (WEIGHTED && kept) wsum += qw[i];
+    }
+    __syncthreads();
+    // Exclusive scan of the M + 1 cell counts (runs per thread, then a
+    // sequential pass over the 256 run totals).
+    {
+      const int per = (M + 1 + kBlock - 1) / kBlock;
+      const int b0 = min(M + 1, tid * per), b1 = min(M + 1, b0 + per);
+      int run = 0;
+      for (int b = b0; b < b1; ++b) run += cnt[b];
+      s_part[tid] = run;
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < kBlock; ++i) {
+          const int v = s_part[i];
+          s_part[i] = acc;
+          acc += v;
+        }
+      }
+      __syncthreads();
+      int acc = s_part[tid];
+      for (int b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        cnt[b] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+    // Scatter into cells (any order inside a cell); cnt becomes cell ends.
+    for (int i = tid; i < n; i += kBlock) {
+      const double ph = ph_u[i];
+      const int cell = ph < 1.5 ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      grp[atomicAdd(&cnt[cell], 1)] = i;
+    }
+    __syncthreads();
+    // Rank = cell start + cell mates before this point in (phase, index).
+    for (int i = tid; i < n; i += kBlock) {
+      const double ph = ph_u[i];
+      const int cell = ph < 1.5 ? (int)min((unsigned)(int)(ph * Md), (unsigned)(M - 1)) : M;
+      const int b = cell == 0 ? 0 : cnt[cell - 1];
+      const int e = cnt[cell];
+      int rank = b;
+      for (int k = b; k < e; ++k) {
+        const int j = grp[k];
+        const double pj = ph_u[j];
+        rank += (pj < ph || (pj == ph && j < i)) ? 1 : 0;
+      }
+      sph[rank] = ph;
+      sq[rank] = q[i];
+      sidx[rank] = i;
+      if (WEIGHTED) sw[rank] = qw[i];
+    }
+    long long W = 0;
+    if (WEIGHTED) {
+      for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+      if ((tid & 63) == 0) s_wsum[tid >> 6] = wsum;
+    }
+    __syncthreads();
+    const int nk = M == 0 ? 0 : cnt[M - 1];  // kept points come first
+    if (WEIGHTED) {
+      for (int k = 0; k < kBlock / 64; ++k) W += s_wsum[k];
+    } else {
+      W = nk;
+    }
+    const double Wd = (double)W;
+    const double qlo = cd.qlo, qhi = cd.qhi;
+
+    // Runs from every start position, four run steps per iteration with
+    // their values loaded together, up to the longest run a box shorter than
+    // qhi in phase can hold.  S and R are summed in FP64, which is
+    // exact here (|q|, w < 2^qbits with qbits <= 63 - 2 bitlen(n) keep
+    // every partial sum below 2^53 at any curve length).  Each step is screened against theta,
+    // the best value any lane of the workgroup has found so far in this
+    // period (s_theta, raised as lanes improve; the lanes' final bests go to
+    // s_vbits as before): a run with
+    // S^2 < theta (1 - 2^-20) R (W - R) can be neither the best nor a tie
+    // of it, so it skips the admissibility tests and the exact comparison.
+    // Candidates are compared without a division (S^2 / den against the
+    // lane's best as cross products).
+    double bnum = 0.0, bden = 1.0;
+    unsigned int btie = 0xFFFFFFFFu;
+    double bS = 0.0, bR = 0.0;
+    for (int r = tid; r < nk; r += kBlock) {
+      const int prev = r == 0 ? nk - 1 : r - 1;
+      const double ph_r = sph[r], ph_prev = sph[prev];
+      if (!(fwd_phase(ph_prev, ph_r, prev, r) > 0.0)) continue;
+      const unsigned long long tb =
+          __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      double thr = __longlong_as_double((long long)tb) * (1.0 - 0x1p-20);
+      // Longest run from r that a box with duty cycle below qhi can hold:
+      // the span from r grows along the phase order, so it is found by
+      // bisection (a run of one point spans nothing).
+      int lmax = 1;
+      {
+        int hi = nk - 1;
+        while (lmax < hi) {
+          const int mid = (lmax + hi + 1) >> 1;
+          int e = r + mid - 1;
+          if (e >= nk) e -= nk;
+          if (fwd_phase(ph_r, sph[e], r, e) < qhi)
+            lmax = mid;
+          else
+            hi = mid - 1;
+        }
+      }
+      double S = 0.0, R = 0.0;
+      int e0 = r;  // first position of the next group of four
+      for (int len = 1; len <= lmax; len += 4) {
+        int idx[4];
+        idx[0] = e0;
+#pragma unroll
+        for (int u = 1; u < 4; ++u) idx[u] = idx[u - 1] + 1 == nk ? 0 : idx[u - 1] + 1;
+        int qv[4], wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          qv[u] = sq[idx[u]];
+          wv[u] = WEIGHTED ? sw[idx[u]] : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int L = len + u;
+          if (L > lmax) break;
+          S += (double)qv[u];
+          R += WEIGHTED ? (double)wv[u] : 1.0;
+          if (DIP && !(S < 0.0)) continue;
+          const double den = R * (Wd - R);
+          const double num = S * S;
+          if (num < thr * den) continue;
+          // Rare: the run passed the screen; its edges must be admissible.
+          const int e = idx[u];
+          const int next = e + 1 == nk ? 0 : e + 1;
+          const double pe = sph[e], pn = sph[next];
+          if (!(fwd_phase(pe, pn, e, next) > 0.0)) continue;
+          const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, pn, prev, next);
+          if (!(gap > qlo)) continue;
+          if (L < a.min_in_points) continue;
+          if (!(den > 0.0) || S == 0.0) continue;
+          const double lhs = num * bden, rhs = bnum * den;
+          const unsigned int tie = (unsigned)L * (unsigned)nk + (unsigned)r;
+          if (lhs > rhs || (lhs == rhs && tie < btie)) {
+            bnum = num;
+            bden = den;
+            btie = tie;
+            bS = S;
+            bR = R;
+            const double v = num / den;
+            thr = fmax(thr, v * (1.0 - 0x1p-20));
+            __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(v),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+        e0 = idx[3] + 1 == nk ? 0 : idx[3] + 1;
+      }
+    }
+    const double bv = bnum > 0.0 ? bnum / bden : 0.0;
+    const unsigned long long vb = (unsigned long long)__double_as_longlong(bv);
+    if (bv > 0.0) atomicMax(&s_vbits, vb);
+    __syncthreads();
+    if (bv > 0.0 && vb == s_vbits) atomicMin(&s_tie, btie);
+    __syncthreads();
+    if (bv > 0.0 && vb == s_vbits && btie == s_tie) {
+      s_bestS = (long long)bS;  // exact integers
+      s_bestR = (long long)bR;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float srf = 0.0f;
+      if (s_vbits == 0ull) {
+        a.sr[r_out] = 0.0f;
+        a.depth[r_out] = NAN;
+        a.jstart[r_out] = -1;
+        a.kwidth[r_out] = -1;
+      } else {
+        const int len = (int)(s_tie / (unsigned)nk);
+        const int r = (int)(s_tie - (unsigned)len * (unsigned)nk);
+        const double scale = WEIGHTED ? ldexp(1.0, cd.ew - cd.es) : ldexp(1.0, -cd.es);
+        const double v = __longlong_as_double((long long)s_vbits);
+        const double Rd = (double)s_bestR;
+        const double den = Rd * (Wd - Rd);
+        srf = (float)(sqrt(v) * scale);
+        a.sr[r_out] = srf;
+        a.depth[r_out] = (float)(-(double)s_bestS * Wd / den * scale);
+        a.jstart[r_out] = sidx[r];
+        a.kwidth[r_out] = sidx[(r + len - 1) % nk];
+      }
+      const unsigned long long ckey = ((unsigned long long)__float_as_uint(srf) << 32) |
+                                      (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+      __hip_atomic_fetch_max(a.best_key + c, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    }  // valid curve
+    __syncthreads();
+  }
+}
+
+template <bool W, bool D, bool G>
+const void *unbinned_fn() {
+  return reinterpret_cast<const void *>(&unbinned_kernel<W, D, G>);
+}
+
+const void *pick_unbinned(bool weighted, bool dip, bool glob) {
+  if (glob) {
+    if (weighted) return dip ? unbinned_fn<true, true, true>() : unbinned_fn<true, false, true>();
+    return dip ? unbinned_fn<false, true, true>() : unbinned_fn<false, false, true>();
+  }
+  if (weighted) return dip ? unbinned_fn<true, true, false>() : unbinned_fn<true, false, false>();
+  return dip ? unbinned_fn<false, true, false>() : unbinned_fn<false, false, false>();
+}
+
+}  // namespace
+
+int64_t unbinned_lds_bytes(int n, bool weighted) {
+  const int64_t N = n < 1 ? 1 : n;
+  const int64_t M = pow2_at_least((int)N);
+  return 8 * N + 8 * N + 4 * N + 4 * N + 4 * N + 4 * (M + 1) + (weighted ? 4 * N : 0);
+}
+
+int launch_unbinned(const SearchArgs &a, bool weighted, bool dip_only, int grid, void *stream) {
+  if (a.nitems <= 0) return 0;
+  const void *fn = pick_unbinned(weighted, dip_only, a.uws != nullptr);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, a.hist_bytes);
+  if (e != hipSuccess) return (int)e;
+  void *args[] = {const_cast<SearchArgs *>(&a)};
+  e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)a.hist_bytes,
+                      (hipStream_t)stream);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipGetLastError();
+}
+
+int unbinned_blocks_per_cu(bool weighted, bool dip_only, bool glob, int lds_bytes,
+                           int *blocks) {
+  const void *fn = pick_unbinned(weighted, dip_only, glob);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kBlock, (size_t)lds_bytes);
+}
+
+}  // namespace bls
