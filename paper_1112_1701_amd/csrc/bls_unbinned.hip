@@ -27,6 +27,13 @@ __host__ __device__ inline int pow2_at_least(int n) {
   return m;
 }
 
+// Array stride of the per-point arrays for curves of up to n points: even,
+// so that every 8-byte array of the layout stays 8-byte aligned.
+__host__ __device__ inline int unbinned_stride(int n) { return n < 1 ? 2 : (n + 1) & ~1; }
+
+// Run ends screened together by one bound (the window of the walk).
+constexpr int kUnbRun = 8;
+
 // Forward phase distance from sorted position i (phase pi) to j (phase pj),
 // one cycle added when the step passes the end of the order.
 __device__ inline double fwd_phase(double pi, double pj, int i, int j) {
@@ -47,19 +54,27 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   __shared__ unsigned int s_tie;
   __shared__ long long s_bestS, s_bestR;
   __shared__ long long s_wsum[kBlock / 64];
+  __shared__ double s_wtot[2 * (kBlock / 64)];
   __shared__ int s_part[kBlock];
 
   const int tid = threadIdx.x;
-  const int N = a.ucap;
-  const int Mc = pow2_at_least(N);
+  const int N = unbinned_stride(a.ucap);
   unsigned char *s_raw = GLOB ? a.uws + (int64_t)blockIdx.x * a.uws_stride : s_lds;
   double *ph_u = reinterpret_cast<double *>(s_raw);
   double *sph = ph_u + N;
   int *sq = reinterpret_cast<int *>(sph + N);
-  int *sidx = sq + N;
+  int *sw = sq + N;  // weighted only
+  int *sidx = sw + (WEIGHTED ? N : 0);
   int *grp = sidx + N;
   int *cnt = grp + N;
-  int *sw = cnt + Mc + 1;   // weighted only
+  // After the ranking: the prefix sums of the values over grp and the cell
+  // counts; the weights' prefix sums over the unsorted phases; the window
+  // bounds over the unsorted phases (unit weights) or over the sorted values
+  // and weights (weighted); the longest runs (unit weights) over the values.
+  double *Pq = reinterpret_cast<double *>(grp);
+  double *Pw = ph_u;
+  float2 *Mb = reinterpret_cast<float2 *>(WEIGHTED ? (void *)sq : (void *)ph_u);
+  int *lm = sq;
 
   unsigned done_mask = 0u;
   SegCache sc = {0, 0, 0, 0};
@@ -183,18 +198,137 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     const double Wd = (double)W;
     const double qlo = cd.qlo, qhi = cd.qhi;
 
-    // Runs from every start position, four run steps per iteration with
-    // their values loaded together, up to the longest run a box shorter than
-    // qhi in phase can hold.  S and R are summed in FP64, which is
-    // exact here (|q|, w < 2^qbits with qbits <= 63 - 2 bitlen(n) keep
-    // every partial sum below 2^53 at any curve length).  Each step is screened against theta,
-    // the best value any lane of the workgroup has found so far in this
-    // period (s_theta, raised as lanes improve; the lanes' final bests go to
-    // s_vbits as before): a run with
-    // S^2 < theta (1 - 2^-20) R (W - R) can be neither the best nor a tie
-    // of it, so it skips the admissibility tests and the exact comparison.
-    // Candidates are compared without a division (S^2 / den against the
-    // lane's best as cross products).
+    // Prefix sums in phase order, Pq[i] = q summed over ranks 0..i (and Pw
+    // for the weights), in FP64: every partial sum is an integer below 2^53
+    // (|q|, w < 2^31 and at most 2^20 points), so each is exact and a run's
+    // sum is a difference of two of them, exact as well.  A thread takes a
+    // contiguous chunk: its total, a scan of the totals across the
+    // workgroup, then the chunk's running sums.
+    {
+      const int per = (nk + kBlock - 1) / kBlock;
+      const int cb = min(nk, tid * per), ce = min(nk, cb + per);
+      double tq = 0.0, tw = 0.0;
+      for (int i = cb; i < ce; ++i) {
+        tq += (double)sq[i];
+        if (WEIGHTED) tw += (double)sw[i];
+      }
+      double xq = tq, xw = tw;  // inclusive scan across the wave
+      const int lane = tid & 63;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double yq = __shfl_up(xq, o, 64);
+        const double yw = WEIGHTED ? __shfl_up(xw, o, 64) : 0.0;
+        if (lane >= o) {
+          xq += yq;
+          if (WEIGHTED) xw += yw;
+        }
+      }
+      if (lane == 63) {
+        s_wtot[tid >> 6] = xq;
+        if (WEIGHTED) s_wtot[kBlock / 64 + (tid >> 6)] = xw;
+      }
+      __syncthreads();  // every thread has read nk and the weight total
+      double rq = xq - tq, rw = xw - tw;
+      for (int w = 0; w < (tid >> 6); ++w) {
+        rq += s_wtot[w];
+        if (WEIGHTED) rw += s_wtot[kBlock / 64 + w];
+      }
+      for (int i = cb; i < ce; ++i) {
+        rq += (double)sq[i];
+        Pq[i] = rq;
+        if (WEIGHTED) {
+          rw += (double)sw[i];
+          Pw[i] = rw;
+        }
+      }
+    }
+    __syncthreads();
+    const double Tq = nk > 0 ? Pq[nk - 1] : 0.0;
+    const double Tw = WEIGHTED ? (nk > 0 ? Pw[nk - 1] : 0.0) : Wd;
+    // Prefix sum at an unwrapped rank x < 2 nk (one cycle's total added past
+    // the end of the order).
+    auto pq_at = [&](int x) { return x >= nk ? Pq[x - nk] + Tq : Pq[x]; };
+    auto pw_at = [&](int x) { return x >= nk ? Pw[x - nk] + Tw : Pw[x]; };
+
+    // Window bounds: for every rank i the largest and smallest prefix sum
+    // over the kUnbRun unwrapped ranks i .. i + kUnbRun - 1, as floats
+    // rounded outwards (a bound needs no more).  And, with unit weights,
+    // the longest run from every start r that a box with duty cycle below
+    // qhi can hold, into lm[r]: the span from r grows along the phase
+    // order, and the longest run from r + 1 ends no earlier than the one
+    // from r, so a thread takes consecutive starts, finds the first one's
+    // end by bisection and moves it forward for the rest.  (A run of one
+    // point spans nothing.)  Weighted curves have no room for lm and
+    // bisect per start in the walk.
+    for (int i = tid; i < nk; i += kBlock) {
+      double hi = -INFINITY, lo = INFINITY;
+      for (int b = 0; b < kUnbRun; ++b) {
+        int x = i + b, wraps = 0;
+        while (x >= nk) {
+          x -= nk;
+          ++wraps;
+        }
+        const double v = Pq[x] + (double)wraps * Tq;
+        hi = fmax(hi, v);
+        lo = fmin(lo, v);
+      }
+      float fh = (float)hi, fl = (float)lo;
+      if ((double)fh < hi) fh = nextafterf(fh, INFINITY);
+      if ((double)fl > lo) fl = nextafterf(fl, -INFINITY);
+      Mb[i] = make_float2(fh, fl);
+    }
+    auto longest_run = [&](int r) {
+      const double ph_r = sph[r];
+      int lmax = 1, hi = nk - 1;
+      while (lmax < hi) {
+        const int mid = (lmax + hi + 1) >> 1;
+        int e = r + mid - 1;
+        if (e >= nk) e -= nk;
+        if (fwd_phase(ph_r, sph[e], r, e) < qhi)
+          lmax = mid;
+        else
+          hi = mid - 1;
+      }
+      return lmax;
+    };
+    if (!WEIGHTED) {
+      const int per = (nk + kBlock - 1) / kBlock;
+      const int rb = min(nk, tid * per), re = min(nk, rb + per);
+      int end = -1;  // last point of the previous start's run, unwrapped
+      for (int r = rb; r < re; ++r) {
+        int lmax;
+        if (end < r) {
+          lmax = longest_run(r);
+        } else {
+          const double ph_r = sph[r];
+          lmax = end - r + 1;
+          while (lmax < nk - 1) {
+            int e = r + lmax;
+            if (e >= nk) e -= nk;
+            if (!(fwd_phase(ph_r, sph[e], r, e) < qhi)) break;
+            ++lmax;
+          }
+        }
+        end = r + lmax - 1;
+        lm[r] = lmax;
+      }
+    }
+    __syncthreads();
+
+    // Runs from every start position.  A run of L points from start r has
+    // S = P(r + L - 1) - P(r - 1) and R = L (or the same difference of the
+    // weight sums), exact, as above.  Runs are screened against theta, the
+    // best value any lane of the workgroup has found so far in this period
+    // (s_theta, raised as lanes improve; the lanes' final bests go to
+    // s_vbits): a run with S^2 < theta (1 - 2^-20) R (W - R) can be neither
+    // the best nor a tie of it.  The ends are taken kUnbRun at a time, and a
+    // window of ends is screened as a whole first: S^2 is at most the
+    // largest |S| over the window (from the window's prefix-sum bounds;
+    // only negative S for dips), and R (W - R) is concave in the growing R,
+    // so its least value over the window is at the first or the last end.
+    // Only a window that passes has its ends scored one by one: the
+    // admissibility tests of the edges and the exact comparison, without a
+    // division (S^2 / den against the lane's best as cross products).
     double bnum = 0.0, bden = 1.0;
     unsigned int btie = 0xFFFFFFFFu;
     double bS = 0.0, bR = 0.0;
@@ -202,53 +336,49 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       const int prev = r == 0 ? nk - 1 : r - 1;
       const double ph_r = sph[r], ph_prev = sph[prev];
       if (!(fwd_phase(ph_prev, ph_r, prev, r) > 0.0)) continue;
-      const unsigned long long tb =
-          __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      double thr = __longlong_as_double((long long)tb) * (1.0 - 0x1p-20);
-      // Longest run from r that a box with duty cycle below qhi can hold:
-      // the span from r grows along the phase order, so it is found by
-      // bisection (a run of one point spans nothing).
-      int lmax = 1;
-      {
-        int hi = nk - 1;
-        while (lmax < hi) {
-          const int mid = (lmax + hi + 1) >> 1;
-          int e = r + mid - 1;
-          if (e >= nk) e -= nk;
-          if (fwd_phase(ph_r, sph[e], r, e) < qhi)
-            lmax = mid;
-          else
-            hi = mid - 1;
-        }
-      }
-      double S = 0.0, R = 0.0;
-      int e0 = r;  // first position of the next group of four
-      for (int len = 1; len <= lmax; len += 4) {
-        int idx[4];
-        idx[0] = e0;
+      double thr = 0.0;
+      const int lmax = WEIGHTED ? longest_run(r) : lm[r];
+      const int eEnd = r + lmax - 1;  // last end, unwrapped
+      const double base = r == 0 ? 0.0 : Pq[r - 1];
+      const double wbase = WEIGHTED ? (r == 0 ? 0.0 : Pw[r - 1]) : 0.0;
+      for (int e = r; e <= eEnd; e += kUnbRun) {
+        // theta as the other lanes have raised it so far (a relaxed read:
+        // any value it returns is a bound some run reached)
+        const unsigned long long tb =
+            __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        thr = fmax(thr, __longlong_as_double((long long)tb) * (1.0 - 0x1p-20));
+        const bool wr = e >= nk;
+        const float2 mb = Mb[wr ? e - nk : e];
+        const double off = wr ? Tq : 0.0;
+        const double up = ((double)mb.x + off) - base;   // >= every S of the window
+        const double dn = base - ((double)mb.y + off);   // >= every -S
+        const double sm = DIP ? fmax(dn, 0.0) : fmax(fmax(up, dn), 0.0);
+        const int eL = min(e + kUnbRun - 1, eEnd);
+        const double R1 = WEIGHTED ? pw_at(e) - wbase : (double)(e - r + 1);
+        const double R2 = WEIGHTED ? pw_at(eL) - wbase : (double)(eL - r + 1);
+        const double g = fmin(R1 * (Wd - R1), R2 * (Wd - R2));
+        if (!(sm * sm >= thr * g)) continue;
+        double Su[kUnbRun], Ru[kUnbRun];
 #pragma unroll
-        for (int u = 1; u < 4; ++u) idx[u] = idx[u - 1] + 1 == nk ? 0 : idx[u - 1] + 1;
-        int qv[4], wv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          qv[u] = sq[idx[u]];
-          wv[u] = WEIGHTED ? sw[idx[u]] : 1;
+        for (int u = 0; u < kUnbRun; ++u) {
+          const int x = min(e + u, eEnd);
+          Su[u] = pq_at(x) - base;
+          Ru[u] = WEIGHTED ? pw_at(x) - wbase : (double)(x - r + 1);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int L = len + u;
-          if (L > lmax) break;
-          S += (double)qv[u];
-          R += WEIGHTED ? (double)wv[u] : 1.0;
+        for (int u = 0; u < kUnbRun; ++u) {
+          if (e + u > eL) break;
+          const int L = e + u - r + 1;
+          const double S = Su[u], R = Ru[u];
           if (DIP && !(S < 0.0)) continue;
           const double den = R * (Wd - R);
           const double num = S * S;
           if (num < thr * den) continue;
           // Rare: the run passed the screen; its edges must be admissible.
-          const int e = idx[u];
-          const int next = e + 1 == nk ? 0 : e + 1;
-          const double pe = sph[e], pn = sph[next];
-          if (!(fwd_phase(pe, pn, e, next) > 0.0)) continue;
+          const int x = e + u >= nk ? e + u - nk : e + u;
+          const int next = x + 1 == nk ? 0 : x + 1;
+          const double pe = sph[x], pn = sph[next];
+          if (!(fwd_phase(pe, pn, x, next) > 0.0)) continue;
           const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, pn, prev, next);
           if (!(gap > qlo)) continue;
           if (L < a.min_in_points) continue;
@@ -267,7 +397,6 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
-        e0 = idx[3] + 1 == nk ? 0 : idx[3] + 1;
       }
     }
     const double bv = bnum > 0.0 ? bnum / bden : 0.0;
@@ -327,7 +456,7 @@ const void *pick_unbinned(bool weighted, bool dip, bool glob) {
 }  // namespace
 
 int64_t unbinned_lds_bytes(int n, bool weighted) {
-  const int64_t N = n < 1 ? 1 : n;
+  const int64_t N = unbinned_stride(n);
   const int64_t M = pow2_at_least((int)N);
   return 8 * N + 8 * N + 4 * N + 4 * N + 4 * N + 4 * (M + 1) + (weighted ? 4 * N : 0);
 }
