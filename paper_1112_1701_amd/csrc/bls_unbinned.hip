@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   __shared__ long long s_bestS, s_bestR;
   __shared__ long long s_wsum[kBlock / 64];
   __shared__ double s_wtot[2 * (kBlock / 64)];
-  __shared__ int s_part[kBlock];
+  __shared__ int s_part[kBlock / 64];
 
   const int tid = threadIdx.x;
   const int N = unbinned_stride(a.ucap);
@@ -133,25 +133,24 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       if (WEIGHTED && kept) wsum += qw[i];
     }
     __syncthreads();
-    // Exclusive scan of the M + 1 cell counts (runs per thread, then a
-    // sequential pass over the 256 run totals).
+    // Exclusive scan of the M + 1 cell counts: a run of cells per thread,
+    // a scan of the run totals across each wave, then across the waves.
     {
       const int per = (M + 1 + kBlock - 1) / kBlock;
       const int b0 = min(M + 1, tid * per), b1 = min(M + 1, b0 + per);
       int run = 0;
       for (int b = b0; b < b1; ++b) run += cnt[b];
-      s_part[tid] = run;
-      __syncthreads();
-      if (tid == 0) {
-        int acc = 0;
-        for (int i = 0; i < kBlock; ++i) {
-          const int v = s_part[i];
-          s_part[i] = acc;
-          acc += v;
-        }
+      int x = run;
+      const int lane = tid & 63;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
       }
+      if (lane == 63) s_part[tid >> 6] = x;
       __syncthreads();
-      int acc = s_part[tid];
+      int acc = x - run;
+      for (int w = 0; w < (tid >> 6); ++w) acc += s_part[w];
       for (int b = b0; b < b1; ++b) {
         const int v = cnt[b];
         cnt[b] = acc;
@@ -262,15 +261,26 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     // bisect per start in the walk.
     for (int i = tid; i < nk; i += kBlock) {
       double hi = -INFINITY, lo = INFINITY;
-      for (int b = 0; b < kUnbRun; ++b) {
-        int x = i + b, wraps = 0;
-        while (x >= nk) {
-          x -= nk;
-          ++wraps;
+      if (i + kUnbRun <= nk) {  // no wrap: the loads go out together
+        double v[kUnbRun];
+#pragma unroll
+        for (int b = 0; b < kUnbRun; ++b) v[b] = Pq[i + b];
+#pragma unroll
+        for (int b = 0; b < kUnbRun; ++b) {
+          hi = fmax(hi, v[b]);
+          lo = fmin(lo, v[b]);
         }
-        const double v = Pq[x] + (double)wraps * Tq;
-        hi = fmax(hi, v);
-        lo = fmin(lo, v);
+      } else {
+        for (int b = 0; b < kUnbRun; ++b) {
+          int x = i + b, wraps = 0;
+          while (x >= nk) {
+            x -= nk;
+            ++wraps;
+          }
+          const double v = Pq[x] + (double)wraps * Tq;
+          hi = fmax(hi, v);
+          lo = fmin(lo, v);
+        }
       }
       float fh = (float)hi, fl = (float)lo;
       if ((double)fh < hi) fh = nextafterf(fh, INFINITY);
@@ -358,43 +368,49 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
         const double R2 = WEIGHTED ? pw_at(eL) - wbase : (double)(eL - r + 1);
         const double g = fmin(R1 * (Wd - R1), R2 * (Wd - R2));
         if (!(sm * sm >= thr * g)) continue;
-        double Su[kUnbRun], Ru[kUnbRun];
+        // The window's ends in two halves, each half's loads together.
+        constexpr int kHalf = kUnbRun / 2;
 #pragma unroll
-        for (int u = 0; u < kUnbRun; ++u) {
-          const int x = min(e + u, eEnd);
-          Su[u] = pq_at(x) - base;
-          Ru[u] = WEIGHTED ? pw_at(x) - wbase : (double)(x - r + 1);
-        }
+        for (int h = 0; h < kUnbRun; h += kHalf) {
+          if (e + h > eL) break;
+          double Pv[kHalf], Wv[kHalf];
 #pragma unroll
-        for (int u = 0; u < kUnbRun; ++u) {
-          if (e + u > eL) break;
-          const int L = e + u - r + 1;
-          const double S = Su[u], R = Ru[u];
-          if (DIP && !(S < 0.0)) continue;
-          const double den = R * (Wd - R);
-          const double num = S * S;
-          if (num < thr * den) continue;
-          // Rare: the run passed the screen; its edges must be admissible.
-          const int x = e + u >= nk ? e + u - nk : e + u;
-          const int next = x + 1 == nk ? 0 : x + 1;
-          const double pe = sph[x], pn = sph[next];
-          if (!(fwd_phase(pe, pn, x, next) > 0.0)) continue;
-          const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, pn, prev, next);
-          if (!(gap > qlo)) continue;
-          if (L < a.min_in_points) continue;
-          if (!(den > 0.0) || S == 0.0) continue;
-          const double lhs = num * bden, rhs = bnum * den;
-          const unsigned int tie = (unsigned)L * (unsigned)nk + (unsigned)r;
-          if (lhs > rhs || (lhs == rhs && tie < btie)) {
-            bnum = num;
-            bden = den;
-            btie = tie;
-            bS = S;
-            bR = R;
-            const double v = num / den;
-            thr = fmax(thr, v * (1.0 - 0x1p-20));
-            __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(v),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          for (int u = 0; u < kHalf; ++u) {
+            const int x = min(e + h + u, eEnd);
+            Pv[u] = pq_at(x);
+            if (WEIGHTED) Wv[u] = pw_at(x);
+          }
+#pragma unroll
+          for (int u = 0; u < kHalf; ++u) {
+            if (e + h + u > eL) break;
+            const int L = e + h + u - r + 1;
+            const double S = Pv[u] - base, R = WEIGHTED ? Wv[u] - wbase : (double)L;
+            if (DIP && !(S < 0.0)) continue;
+            const double den = R * (Wd - R);
+            const double num = S * S;
+            if (num < thr * den) continue;
+            // Rare: the run passed the screen; its edges must be admissible.
+            const int x = e + h + u >= nk ? e + h + u - nk : e + h + u;
+            const int next = x + 1 == nk ? 0 : x + 1;
+            const double pe = sph[x], pn = sph[next];
+            if (!(fwd_phase(pe, pn, x, next) > 0.0)) continue;
+            const double gap = prev == next ? 1.0 : fwd_phase(ph_prev, pn, prev, next);
+            if (!(gap > qlo)) continue;
+            if (L < a.min_in_points) continue;
+            if (!(den > 0.0) || S == 0.0) continue;
+            const double lhs = num * bden, rhs = bnum * den;
+            const unsigned int tie = (unsigned)L * (unsigned)nk + (unsigned)r;
+            if (lhs > rhs || (lhs == rhs && tie < btie)) {
+              bnum = num;
+              bden = den;
+              btie = tie;
+              bS = S;
+              bR = R;
+              const double v = num / den;
+              thr = fmax(thr, v * (1.0 - 0x1p-20));
+              __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(v),
+                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
           }
         }
       }
