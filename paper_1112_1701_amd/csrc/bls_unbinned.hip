@@ -62,19 +62,19 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
   unsigned char *s_raw = GLOB ? a.uws + (int64_t)blockIdx.x * a.uws_stride : s_lds;
   double *ph_u = reinterpret_cast<double *>(s_raw);
   double *sph = ph_u + N;
-  int *sq = reinterpret_cast<int *>(sph + N);
+  int *sidx = reinterpret_cast<int *>(sph + N);
+  int *sq = sidx + N;
   int *sw = sq + N;  // weighted only
-  int *sidx = sw + (WEIGHTED ? N : 0);
-  int *grp = sidx + N;
+  int *grp = sw + (WEIGHTED ? N : 0);
   int *cnt = grp + N;
-  // After the ranking: the prefix sums of the values over grp and the cell
-  // counts; the weights' prefix sums over the unsorted phases; the window
-  // bounds over the unsorted phases (unit weights) or over the sorted values
-  // and weights (weighted); the longest runs (unit weights) over the values.
-  double *Pq = reinterpret_cast<double *>(grp);
-  double *Pw = ph_u;
-  float2 *Mb = reinterpret_cast<float2 *>(WEIGHTED ? (void *)sq : (void *)ph_u);
-  int *lm = sq;
+  // After the ranking: the prefix sums of the values over the unsorted
+  // phases, those of the weights over grp and the cell counts (weighted;
+  // unit weights keep the cell counts, which place the longest runs), and
+  // the window bounds over the values and the next array (the weights or
+  // grp), 8 bytes per point.
+  double *Pq = ph_u;
+  double *Pw = reinterpret_cast<double *>(grp);
+  float2 *Mb = reinterpret_cast<float2 *>(sq);
 
   unsigned done_mask = 0u;
   SegCache sc = {0, 0, 0, 0};
@@ -251,14 +251,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
 
     // Window bounds: for every rank i the largest and smallest prefix sum
     // over the kUnbRun unwrapped ranks i .. i + kUnbRun - 1, as floats
-    // rounded outwards (a bound needs no more).  And, with unit weights,
-    // the longest run from every start r that a box with duty cycle below
-    // qhi can hold, into lm[r]: the span from r grows along the phase
-    // order, and the longest run from r + 1 ends no earlier than the one
-    // from r, so a thread takes consecutive starts, finds the first one's
-    // end by bisection and moves it forward for the rest.  (A run of one
-    // point spans nothing.)  Weighted curves have no room for lm and
-    // bisect per start in the walk.
+    // rounded outwards (a bound needs no more).
     for (int i = tid; i < nk; i += kBlock) {
       double hi = -INFINITY, lo = INFINITY;
       if (i + kUnbRun <= nk) {  // no wrap: the loads go out together
@@ -287,43 +280,44 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       if ((double)fl > lo) fl = nextafterf(fl, -INFINITY);
       Mb[i] = make_float2(fh, fl);
     }
+    __syncthreads();
+
+    // The longest run from start r that a box with duty cycle below qhi can
+    // hold: runs end at r + L - 1, and the span from r grows along the
+    // phase order, so the first end u past r whose span reaches qhi gives
+    // L = u - r (at most nk - 1; a run of one point spans nothing).  With
+    // unit weights the fine grid of the sort places phase(r) + qhi near that
+    // end: the first rank of its cell is the guess, and exact span tests
+    // move it to the boundary (about one point per cell).  Weighted curves
+    // have no room left for the cell counts and bisect.
+    auto spans_less = [&](int r, double ph_r, int u) {  // end u unwrapped
+      const int e = u >= nk ? u - nk : u;
+      return fwd_phase(ph_r, sph[e], r, e) < qhi;
+    };
     auto longest_run = [&](int r) {
       const double ph_r = sph[r];
-      int lmax = 1, hi = nk - 1;
-      while (lmax < hi) {
-        const int mid = (lmax + hi + 1) >> 1;
-        int e = r + mid - 1;
-        if (e >= nk) e -= nk;
-        if (fwd_phase(ph_r, sph[e], r, e) < qhi)
-          lmax = mid;
-        else
-          hi = mid - 1;
-      }
-      return lmax;
-    };
-    if (!WEIGHTED) {
-      const int per = (nk + kBlock - 1) / kBlock;
-      const int rb = min(nk, tid * per), re = min(nk, rb + per);
-      int end = -1;  // last point of the previous start's run, unwrapped
-      for (int r = rb; r < re; ++r) {
-        int lmax;
-        if (end < r) {
-          lmax = longest_run(r);
-        } else {
-          const double ph_r = sph[r];
-          lmax = end - r + 1;
-          while (lmax < nk - 1) {
-            int e = r + lmax;
-            if (e >= nk) e -= nk;
-            if (!(fwd_phase(ph_r, sph[e], r, e) < qhi)) break;
-            ++lmax;
-          }
+      if (WEIGHTED) {
+        int lmax = 1, hi = nk - 1;
+        while (lmax < hi) {
+          const int mid = (lmax + hi + 1) >> 1;
+          if (spans_less(r, ph_r, r + mid - 1))
+            lmax = mid;
+          else
+            hi = mid - 1;
         }
-        end = r + lmax - 1;
-        lm[r] = lmax;
+        return lmax;
       }
-    }
-    __syncthreads();
+      if (nk <= 2) return 1;
+      const double t = ph_r + qhi;
+      const bool wr = t >= 1.0;
+      const int cell = (int)min((unsigned)(int)((wr ? t - 1.0 : t) * Md), (unsigned)(M - 1));
+      int u = (cell == 0 ? 0 : cnt[cell - 1]) + (wr ? nk : 0);
+      const int lo = r + 1, hi = r + nk - 1;
+      u = min(max(u, lo), hi);
+      while (u < hi && spans_less(r, ph_r, u)) ++u;
+      while (u > lo && !spans_less(r, ph_r, u - 1)) --u;
+      return u - r;
+    };
 
     // Runs from every start position.  A run of L points from start r has
     // S = P(r + L - 1) - P(r - 1) and R = L (or the same difference of the
@@ -347,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       const double ph_r = sph[r], ph_prev = sph[prev];
       if (!(fwd_phase(ph_prev, ph_r, prev, r) > 0.0)) continue;
       double thr = 0.0;
-      const int lmax = WEIGHTED ? longest_run(r) : lm[r];
+      const int lmax = longest_run(r);
       const int eEnd = r + lmax - 1;  // last end, unwrapped
       const double base = r == 0 ? 0.0 : Pq[r - 1];
       const double wbase = WEIGHTED ? (r == 0 ? 0.0 : Pw[r - 1]) : 0.0;
