@@ -40,8 +40,13 @@ struct Req {
   double submit_s = 0, admit_s = 0, done_s = 0;
   int status = BLS_ERR_BUSY;
   bool finished = false;
+  // results: in the pinned result pool when it had room (copied without a
+  // wait), else in these vectors; o_* point at whichever holds them
+  size_t res_off = Arena::kFail;
   std::vector<float> sr, depth;
   std::vector<int32_t> js, ks;
+  const float *o_sr = nullptr, *o_depth = nullptr;
+  const int32_t *o_js = nullptr, *o_ks = nullptr;
   int64_t best = -1;
   int slot = -1;
   size_t pt_off = 0, pr_off = 0;
@@ -59,6 +64,18 @@ struct Tick {
   int nu = 0;
   std::vector<TickSegment> segs;
 };
+
+// Result copies of the requests a tick finished, queued on the copy stream;
+// ev completes when they have landed in the pinned result pool.
+struct Collect {
+  hipEvent_t ev = nullptr;
+  std::vector<Req *> reqs;
+};
+
+// Bytes of a request's block in the pinned result pool: SR, depth, first and
+// last bin (4 B per period each, in that order), the best key (8 B) and the
+// curve status (4 B, padded).
+size_t result_bytes(int64_t np) { return 16 * (size_t)np + 16; }
 
 // Device bytes a request holds while resident (arena elements, aligned).
 int64_t request_bytes(int64_t n, int64_t np) {
@@ -90,6 +107,7 @@ struct bls_server {
   double *d_t = nullptr, *d_x = nullptr, *d_w = nullptr, *d_dt = nullptr, *d_per = nullptr;
   int32_t *d_q = nullptr, *d_qw = nullptr, *d_js = nullptr, *d_ks = nullptr;
   float *d_sr = nullptr, *d_depth = nullptr;
+  void *d_res = nullptr;  // d_sr, d_depth, d_js, d_ks: one block, cap_per apart
   CurveDesc *d_curves = nullptr, *h_curves = nullptr;
   unsigned long long *d_keys = nullptr;
   int64_t *d_seg_start[kTickBuffers] = {}, *h_seg_start[kTickBuffers] = {};
@@ -102,6 +120,10 @@ struct bls_server {
   Arena pts_arena, per_arena;
   char *h_pool = nullptr;   // pinned staging for request inputs
   Arena pool_arena;
+  char *h_res = nullptr;    // pinned result pool (blocks of result_bytes)
+  Arena res_arena;
+  std::deque<Collect> collecting;
+  std::vector<hipEvent_t> ev_free;
   std::vector<Req *> slots;
   std::deque<Req *> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
@@ -275,30 +297,88 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
   return hipEventRecord(s->ev_e[b], st);
 }
 
-// Copy a finished request's results to the host (the tick that completed
-// its last tile has finished, so nothing on the device still writes them).
-hipError_t collect_request(bls_server *s, Req *r) {
+// Results of a finished request (the tick that completed its last tile has
+// finished, so nothing on the device still writes them).  With a block in
+// the pinned result pool the copies are queued on the copy stream and the
+// request completes once they have landed (*queued); without one they are
+// copied into host vectors at once.
+hipError_t collect_request(bls_server *s, Req *r, bool *queued) {
   const size_t np = (size_t)r->np;
+  hipStream_t cs = s->copy_stream;
+  hipError_t e;
+  *queued = false;
+  if (r->res_off != Arena::kFail) {
+    char *b = s->h_res + r->res_off;
+    // the four result arrays are rows of one pitched block on the device
+    if ((e = hipMemcpy2DAsync(b, np * 4, s->d_sr + r->pr_off, (size_t)s->cap_per * 4, np * 4, 4,
+                              hipMemcpyDeviceToHost, cs)) ||
+        (e = hipMemcpyAsync(b + 16 * np, s->d_keys + r->slot, 8, hipMemcpyDeviceToHost, cs)) ||
+        (e = hipMemcpyAsync(b + 16 * np + 8, &s->d_curves[r->slot].status, 4,
+                            hipMemcpyDeviceToHost, cs)))
+      return e;
+    *queued = true;
+    return hipSuccess;
+  }
   r->sr.resize(np);
   r->depth.resize(np);
   r->js.resize(np);
   r->ks.resize(np);
   unsigned long long key = 0;
-  CurveDesc cd;
-  hipStream_t cs = s->copy_stream;
-  hipError_t e;
+  int32_t status = 0;
   if ((e = hipMemcpyAsync(r->sr.data(), s->d_sr + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
       (e = hipMemcpyAsync(r->depth.data(), s->d_depth + r->pr_off, np * 4, hipMemcpyDeviceToHost,
                           cs)) ||
       (e = hipMemcpyAsync(r->js.data(), s->d_js + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
       (e = hipMemcpyAsync(r->ks.data(), s->d_ks + r->pr_off, np * 4, hipMemcpyDeviceToHost, cs)) ||
       (e = hipMemcpyAsync(&key, s->d_keys + r->slot, 8, hipMemcpyDeviceToHost, cs)) ||
-      (e = hipMemcpyAsync(&cd, s->d_curves + r->slot, sizeof cd, hipMemcpyDeviceToHost, cs)) ||
+      (e = hipMemcpyAsync(&status, &s->d_curves[r->slot].status, 4, hipMemcpyDeviceToHost, cs)) ||
       (e = hipStreamSynchronize(cs)))
     return e;
+  r->o_sr = r->sr.data();
+  r->o_depth = r->depth.data();
+  r->o_js = r->js.data();
+  r->o_ks = r->ks.data();
   r->best = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
-  r->status = cd.status == kCurveOk ? BLS_OK : BLS_ERR_INVALID_ARG;
+  r->status = status == kCurveOk ? BLS_OK : BLS_ERR_INVALID_ARG;
   return hipSuccess;
+}
+
+// Key, status and result pointers of a request whose queued copies landed.
+void read_pinned_results(bls_server *s, Req *r) {
+  const size_t np = (size_t)r->np;
+  const char *b = s->h_res + r->res_off;
+  unsigned long long key = 0;
+  int32_t status = 0;
+  memcpy(&key, b + 16 * np, 8);
+  memcpy(&status, b + 16 * np + 8, 4);
+  r->o_sr = reinterpret_cast<const float *>(b);
+  r->o_depth = r->o_sr + np;
+  r->o_js = reinterpret_cast<const int32_t *>(r->o_depth + np);
+  r->o_ks = r->o_js + np;
+  r->best = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+  r->status = status == kCurveOk ? BLS_OK : BLS_ERR_INVALID_ARG;
+}
+
+// A request whose results are on the host: its device room and slot go back
+// (the lock is held).
+void complete_request(bls_server *s, Req *r) {
+  r->done_s = now_s(s);
+  r->finished = true;
+  s->slots[r->slot] = nullptr;
+  s->pts_arena.release(r->pt_off);
+  if (r->pin_off != Arena::kFail) {
+    s->pool_arena.release(r->pin_off);  // its copies finished long ago
+    r->pin_off = Arena::kFail;
+  }
+  s->per_arena.release(r->pr_off);
+  if (r->status == BLS_OK) {
+    s->completed++;
+    s->pp_done += r->pp;
+    s->evals_done += r->evals;
+    s->lat.add((r->done_s - r->submit_s) * 1e3);
+  } else {
+    s->failed++;
+  }
 }
 
 void scheduler(bls_server *s) {
@@ -332,34 +412,59 @@ void scheduler(bls_server *s) {
       }
       s->buf_busy[tk.buf] = false;
       s->inflight.pop_front();
-      for (Req *r : done) {
+      if (!done.empty()) {
+        Collect col;
+        std::vector<Req *> now;  // copied at once (no room in the result pool)
         lk.unlock();
-        hipError_t e = collect_request(s, r);
+        hipError_t e = hipSuccess;
+        for (Req *r : done) {
+          bool queued = false;
+          if (e == hipSuccess) e = collect_request(s, r, &queued);
+          (queued ? col.reqs : now).push_back(r);
+        }
+        if (e == hipSuccess && !col.reqs.empty()) {
+          if (!s->ev_free.empty()) {
+            col.ev = s->ev_free.back();
+            s->ev_free.pop_back();
+          } else {
+            e = hipEventCreateWithFlags(&col.ev, hipEventDisableTiming);
+          }
+          if (e == hipSuccess) e = hipEventRecord(col.ev, s->copy_stream);
+        }
         lk.lock();
         if (e != hipSuccess) {
+          if (col.ev) s->ev_free.push_back(col.ev);
+          s->device_error = BLS_ERR_DEVICE;
           srv_hip(s, e, "collect results");
           fail_all(s, BLS_ERR_DEVICE);
           break;
         }
-        r->done_s = now_s(s);
-        r->finished = true;
-        s->slots[r->slot] = nullptr;
-        s->pts_arena.release(r->pt_off);
-        if (r->pin_off != Arena::kFail) {
-          s->pool_arena.release(r->pin_off);  // its copies finished long ago
-          r->pin_off = Arena::kFail;
-        }
-        s->per_arena.release(r->pr_off);
-        if (r->status == BLS_OK) {
-          s->completed++;
-          s->pp_done += r->pp;
-          s->evals_done += r->evals;
-          s->lat.add((r->done_s - r->submit_s) * 1e3);
-        } else {
-          s->failed++;
-        }
+        for (Req *r : now) complete_request(s, r);
+        if (!now.empty()) s->cv_done.notify_all();
+        if (!col.reqs.empty()) s->collecting.push_back(std::move(col));
       }
-      if (!done.empty()) s->cv_done.notify_all();
+      progressed = true;
+    }
+    if (s->device_error) break;
+
+    // 1b. Result copies that have landed: their requests are done.
+    while (!s->collecting.empty()) {
+      Collect &col = s->collecting.front();
+      hipError_t q = hipEventQuery(col.ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) {
+        s->device_error = BLS_ERR_DEVICE;
+        srv_hip(s, q, "result copies");
+        fail_all(s, BLS_ERR_DEVICE);
+        break;
+      }
+      for (Req *r : col.reqs) {
+        read_pinned_results(s, r);
+        complete_request(s, r);
+      }
+      s->ev_free.push_back(col.ev);
+      s->collecting.pop_front();
+      s->cv_done.notify_all();
       progressed = true;
     }
     if (s->device_error) break;
@@ -448,7 +553,7 @@ void scheduler(bls_server *s) {
     }
 
     if (!progressed) {
-      if (s->inflight.empty())
+      if (s->inflight.empty() && s->collecting.empty())
         s->cv_work.wait_for(lk, std::chrono::milliseconds(50));
       else
         s->cv_work.wait_for(lk, std::chrono::microseconds(50));
@@ -532,12 +637,17 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
   } req[] = {{(void **)&s->d_t, 8 * P},        {(void **)&s->d_x, 8 * P},
              {(void **)&s->d_w, 8 * P},        {(void **)&s->d_dt, 8 * P},
              {(void **)&s->d_q, 4 * P},        {(void **)&s->d_qw, 4 * P},
-             {(void **)&s->d_per, 8 * Q},      {(void **)&s->d_sr, 4 * Q},
-             {(void **)&s->d_depth, 4 * Q},    {(void **)&s->d_js, 4 * Q},
-             {(void **)&s->d_ks, 4 * Q},       {(void **)&s->d_curves, sizeof(CurveDesc) * M},
+             {(void **)&s->d_per, 8 * Q},      {(void **)&s->d_res, 16 * Q},
+             {(void **)&s->d_curves, sizeof(CurveDesc) * M},
              {(void **)&s->d_keys, 8 * M}};
   for (auto &r : req)
     if ((e = device_alloc(r.ptr, r.bytes))) return fail(srv_hip(s, e, "allocate arena"));
+  // the result arrays as rows of one block, so that one pitched copy takes
+  // a request's four
+  s->d_sr = static_cast<float *>(s->d_res);
+  s->d_depth = s->d_sr + Q;
+  s->d_js = reinterpret_cast<int32_t *>(s->d_depth + Q);
+  s->d_ks = s->d_js + Q;
   for (int b = 0; b < kTickBuffers; ++b) {
     if ((e = device_alloc((void **)&s->d_seg_start[b], 8 * (M + 2))) ||
         (e = device_alloc((void **)&s->d_seg_curve[b], 4 * M)) ||
@@ -564,6 +674,14 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
       s->pool_arena.reset(pool, 256);
     else
       s->h_pool = nullptr;
+    // pinned results: half the device arena, at most 2 GiB (a finished
+    // request holds its block until it is released); results that do not fit
+    // are copied into pageable memory with a wait instead
+    const size_t rpool = (size_t)std::min<int64_t>(cfg.arena_bytes / 2, int64_t(2) << 30);
+    if (hipHostMalloc((void **)&s->h_res, rpool, 0) == hipSuccess)
+      s->res_arena.reset(rpool, 256);
+    else
+      s->h_res = nullptr;
   }
   // 20 KB of LDS per request tile leaves room for 8 workgroups per CU.  On
   // the serving sweep it beat the batch path's 32 KB (p99 at 1000 requests/s
@@ -627,9 +745,10 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
     const size_t n8 = (size_t)q->n * 8, p8 = (size_t)q->nperiods * 8;
     const size_t need = 3 * ((n8 + 255) & ~size_t(255)) + p8;
     size_t off = Arena::kFail;
-    if (s->h_pool) {
+    if (s->h_pool || s->h_res) {
       std::lock_guard<std::mutex> g(s->mu);
-      off = s->pool_arena.alloc(need);
+      if (s->h_pool) off = s->pool_arena.alloc(need);
+      if (s->h_res) r->res_off = s->res_arena.alloc(result_bytes(q->nperiods));
     }
     if (off != Arena::kFail) {
       char *base = s->h_pool + off;
@@ -677,6 +796,7 @@ int bls_server_submit(bls_server *s, const bls_request *q, uint64_t *ticket) {
     reject = srv_error(s, BLS_ERR_CAPACITY, "request larger than the server's device arena");
   if (reject != BLS_OK) {
     if (r->pin_off != Arena::kFail) s->pool_arena.release(r->pin_off);
+    if (r->res_off != Arena::kFail) s->res_arena.release(r->res_off);
     return reject;
   }
   r->ticket = s->next_ticket++;
@@ -693,10 +813,10 @@ static void fill_result(const Req *r, bls_result *out) {
   memset(out, 0, sizeof *out);
   out->status = r->status;
   out->nperiods = r->status == BLS_OK ? r->np : 0;
-  out->sr = r->sr.data();
-  out->depth = r->depth.data();
-  out->jstart = r->js.data();
-  out->kwidth = r->ks.data();
+  out->sr = r->o_sr;
+  out->depth = r->o_depth;
+  out->jstart = r->o_js;
+  out->kwidth = r->o_ks;
   out->best_index = r->best;
   out->submit_s = r->submit_s;
   out->admit_s = r->admit_s;
@@ -735,6 +855,7 @@ int bls_server_release(bls_server *s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end() || !it->second->finished)
     return srv_error(s, BLS_ERR_INVALID_ARG, "unknown or unfinished ticket");
+  if (it->second->res_off != Arena::kFail) s->res_arena.release(it->second->res_off);
   s->reqs.erase(it);
   return BLS_OK;
 }
@@ -817,10 +938,12 @@ int bls_server_destroy(bls_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
   for (void *d : {(void *)s->d_t, (void *)s->d_x, (void *)s->d_w, (void *)s->d_dt,
-                  (void *)s->d_q, (void *)s->d_qw, (void *)s->d_per, (void *)s->d_sr,
-                  (void *)s->d_depth, (void *)s->d_js, (void *)s->d_ks, (void *)s->d_curves,
-                  (void *)s->d_keys})
+                  (void *)s->d_q, (void *)s->d_qw, (void *)s->d_per, s->d_res,
+                  (void *)s->d_curves, (void *)s->d_keys})
     if (d) (void)hipFree(d);
+  for (const Collect &c : s->collecting)
+    if (c.ev) (void)hipEventDestroy(c.ev);
+  for (hipEvent_t ev : s->ev_free) (void)hipEventDestroy(ev);
   for (int b = 0; b < kTickBuffers; ++b) {
     for (void *d : {(void *)s->d_seg_start[b], (void *)s->d_seg_curve[b],
                     (void *)s->d_seg_tile0[b], (void *)s->d_counter[b]})
@@ -833,6 +956,7 @@ int bls_server_destroy(bls_server *s) {
   }
   if (s->h_curves) (void)hipHostFree(s->h_curves);
   if (s->h_pool) (void)hipHostFree(s->h_pool);
+  if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;
