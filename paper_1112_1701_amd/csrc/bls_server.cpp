@@ -105,14 +105,17 @@ struct bls_server {
   int64_t arena_budget = 0;   // bytes of resident requests allowed at once
   int64_t bytes_peak = 0;     // largest bytes held at once (both regions)
   double *d_t = nullptr, *d_x = nullptr, *d_w = nullptr, *d_dt = nullptr, *d_per = nullptr;
+  void *d_txw = nullptr;  // d_t, d_x, d_w: one block, cap_pts apart
   int32_t *d_q = nullptr, *d_qw = nullptr, *d_js = nullptr, *d_ks = nullptr;
   float *d_sr = nullptr, *d_depth = nullptr;
   void *d_res = nullptr;  // d_sr, d_depth, d_js, d_ks: one block, cap_per apart
   CurveDesc *d_curves = nullptr, *h_curves = nullptr;
   unsigned long long *d_keys = nullptr;
-  int64_t *d_seg_start[kTickBuffers] = {}, *h_seg_start[kTickBuffers] = {};
-  int32_t *d_seg_curve[kTickBuffers] = {}, *h_seg_curve[kTickBuffers] = {};
-  int32_t *d_seg_tile0[kTickBuffers] = {}, *h_seg_tile0[kTickBuffers] = {};
+  // a tick's segment arrays (starts, curves, first tiles), packed for its
+  // segment count into one block per buffer and sent in one copy
+  char *d_seg[kTickBuffers] = {}, *h_seg[kTickBuffers] = {};
+  int64_t *d_seg_start[kTickBuffers] = {};
+  int32_t *d_seg_curve[kTickBuffers] = {}, *d_seg_tile0[kTickBuffers] = {};
   unsigned long long *d_counter[kTickBuffers] = {};
   hipEvent_t ev_s[kTickBuffers] = {}, ev_e[kTickBuffers] = {};
   bool buf_busy[kTickBuffers] = {};
@@ -202,11 +205,19 @@ hipError_t start_request(bls_server *s, Req *r) {
   hipStream_t st = s->stream;
   hipError_t e;
   const size_t n = (size_t)r->n, np = (size_t)r->np;
-  if ((e = hipMemcpyAsync(s->d_t + r->pt_off, r->pt, n * 8, hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(s->d_x + r->pt_off, r->px, n * 8, hipMemcpyHostToDevice, st)) ||
-      (r->weighted &&
-       (e = hipMemcpyAsync(s->d_w + r->pt_off, r->pw, n * 8, hipMemcpyHostToDevice, st))) ||
-      (e = hipMemcpyAsync(s->d_per + r->pr_off, r->pper, np * 8, hipMemcpyHostToDevice,
+  if (r->pin_off != Arena::kFail) {
+    // staged rows at equal pitch in the pinned pool: one pitched copy
+    const size_t step = (size_t)(r->px - r->pt) * 8;
+    if ((e = hipMemcpy2DAsync(s->d_t + r->pt_off, (size_t)s->cap_pts * 8, r->pt, step, n * 8,
+                              r->weighted ? 3 : 2, hipMemcpyHostToDevice, st)))
+      return e;
+  } else if ((e = hipMemcpyAsync(s->d_t + r->pt_off, r->pt, n * 8, hipMemcpyHostToDevice, st)) ||
+             (e = hipMemcpyAsync(s->d_x + r->pt_off, r->px, n * 8, hipMemcpyHostToDevice, st)) ||
+             (r->weighted && (e = hipMemcpyAsync(s->d_w + r->pt_off, r->pw, n * 8,
+                                                 hipMemcpyHostToDevice, st)))) {
+    return e;
+  }
+  if ((e = hipMemcpyAsync(s->d_per + r->pr_off, r->pper, np * 8, hipMemcpyHostToDevice,
                           st)) ||
       (e = hipMemcpyAsync(s->d_curves + r->slot, &d, sizeof d, hipMemcpyHostToDevice, st)))
     return e;
@@ -264,29 +275,33 @@ hipError_t launch_tick(bls_server *s, Tick &tk) {
   const int nseg = (int)tk.segs.size();
   const int nu = tk.nu, nw = nseg - nu;
   // seg_start: the unit-weight launch's nu + 1 entries, then the weighted
-  // launch's nw + 1; seg_curve and seg_tile0: nu, then nw entries
+  // launch's nw + 1; seg_curve and seg_tile0: nu, then nw entries.  Packed
+  // in that order: 8 (nseg + 2) + 4 nseg + 4 nseg bytes.
+  const size_t o_curve = 8 * (size_t)(nseg + 2), o_tile0 = o_curve + 4 * (size_t)nseg;
+  int64_t *h_start = reinterpret_cast<int64_t *>(s->h_seg[b]);
+  int32_t *h_curve = reinterpret_cast<int32_t *>(s->h_seg[b] + o_curve);
+  int32_t *h_tile0 = reinterpret_cast<int32_t *>(s->h_seg[b] + o_tile0);
+  s->d_seg_start[b] = reinterpret_cast<int64_t *>(s->d_seg[b]);
+  s->d_seg_curve[b] = reinterpret_cast<int32_t *>(s->d_seg[b] + o_curve);
+  s->d_seg_tile0[b] = reinterpret_cast<int32_t *>(s->d_seg[b] + o_tile0);
   int64_t items[2] = {0, 0};
   int hist[2] = {0, 0};
   for (int i = 0; i < nseg; ++i) {
     const TickSegment &g = tk.segs[i];
     const int kind = i < nu ? 0 : 1;
-    s->h_seg_start[b][i + kind] = items[kind];
-    s->h_seg_curve[b][i] = g.slot;
-    s->h_seg_tile0[b][i] = g.tile0;
+    h_start[i + kind] = items[kind];
+    h_curve[i] = g.slot;
+    h_tile0[i] = g.tile0;
     items[kind] += g.ntiles;
     const Req *r = s->slots[g.slot];
     hist[kind] = std::max(hist[kind], r->tile * r->hstride * 8 * (kind ? 2 : 1));
   }
-  s->h_seg_start[b][nu] = items[0];
-  s->h_seg_start[b][nseg + 1] = items[1];
+  h_start[nu] = items[0];
+  h_start[nseg + 1] = items[1];
   hipStream_t st = s->stream;
   hipError_t e;
-  if ((e = hipMemcpyAsync(s->d_seg_start[b], s->h_seg_start[b], 8 * (nseg + 2),
-                          hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(s->d_seg_curve[b], s->h_seg_curve[b], 4 * nseg, hipMemcpyHostToDevice,
-                          st)) ||
-      (e = hipMemcpyAsync(s->d_seg_tile0[b], s->h_seg_tile0[b], 4 * nseg, hipMemcpyHostToDevice,
-                          st)))
+  if ((e = hipMemcpyAsync(s->d_seg[b], s->h_seg[b], o_tile0 + 4 * (size_t)nseg,
+                          hipMemcpyHostToDevice, st)))
     return e;
   // eight counters: the unit-weight launch takes the first, the weighted the fifth
   if ((e = (hipError_t)launch_fill(s->d_counter[b], nullptr, 0, st))) return e;
@@ -634,29 +649,27 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
   struct {
     void **ptr;
     size_t bytes;
-  } req[] = {{(void **)&s->d_t, 8 * P},        {(void **)&s->d_x, 8 * P},
-             {(void **)&s->d_w, 8 * P},        {(void **)&s->d_dt, 8 * P},
+  } req[] = {{(void **)&s->d_txw, 24 * P},     {(void **)&s->d_dt, 8 * P},
              {(void **)&s->d_q, 4 * P},        {(void **)&s->d_qw, 4 * P},
              {(void **)&s->d_per, 8 * Q},      {(void **)&s->d_res, 16 * Q},
              {(void **)&s->d_curves, sizeof(CurveDesc) * M},
              {(void **)&s->d_keys, 8 * M}};
   for (auto &r : req)
     if ((e = device_alloc(r.ptr, r.bytes))) return fail(srv_hip(s, e, "allocate arena"));
-  // the result arrays as rows of one block, so that one pitched copy takes
-  // a request's four
+  // times, values and weights as rows of one block, and the result arrays
+  // as rows of another, so that one pitched copy moves a request's rows
+  s->d_t = static_cast<double *>(s->d_txw);
+  s->d_x = s->d_t + P;
+  s->d_w = s->d_x + P;
   s->d_sr = static_cast<float *>(s->d_res);
   s->d_depth = s->d_sr + Q;
   s->d_js = reinterpret_cast<int32_t *>(s->d_depth + Q);
   s->d_ks = s->d_js + Q;
   for (int b = 0; b < kTickBuffers; ++b) {
-    if ((e = device_alloc((void **)&s->d_seg_start[b], 8 * (M + 2))) ||
-        (e = device_alloc((void **)&s->d_seg_curve[b], 4 * M)) ||
-        (e = device_alloc((void **)&s->d_seg_tile0[b], 4 * M)) ||
+    if ((e = device_alloc((void **)&s->d_seg[b], 16 * (M + 1))) ||
         (e = device_alloc((void **)&s->d_counter[b], 64)))
       return fail(srv_hip(s, e, "allocate tick buffers"));
-    if ((e = hipHostMalloc((void **)&s->h_seg_start[b], 8 * (M + 2), 0)) ||
-        (e = hipHostMalloc((void **)&s->h_seg_curve[b], 4 * M, 0)) ||
-        (e = hipHostMalloc((void **)&s->h_seg_tile0[b], 4 * M, 0)))
+    if ((e = hipHostMalloc((void **)&s->h_seg[b], 16 * (M + 1), 0)))
       return fail(srv_hip(s, e, "allocate pinned tick buffers"));
     if ((e = hipEventCreate(&s->ev_s[b])) || (e = hipEventCreate(&s->ev_e[b])))
       return fail(srv_hip(s, e, "create events"));
@@ -937,7 +950,7 @@ int bls_server_destroy(bls_server *s) {
   }
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
-  for (void *d : {(void *)s->d_t, (void *)s->d_x, (void *)s->d_w, (void *)s->d_dt,
+  for (void *d : {s->d_txw, (void *)s->d_dt,
                   (void *)s->d_q, (void *)s->d_qw, (void *)s->d_per, s->d_res,
                   (void *)s->d_curves, (void *)s->d_keys})
     if (d) (void)hipFree(d);
@@ -945,12 +958,9 @@ int bls_server_destroy(bls_server *s) {
     if (c.ev) (void)hipEventDestroy(c.ev);
   for (hipEvent_t ev : s->ev_free) (void)hipEventDestroy(ev);
   for (int b = 0; b < kTickBuffers; ++b) {
-    for (void *d : {(void *)s->d_seg_start[b], (void *)s->d_seg_curve[b],
-                    (void *)s->d_seg_tile0[b], (void *)s->d_counter[b]})
+    for (void *d : {(void *)s->d_seg[b], (void *)s->d_counter[b]})
       if (d) (void)hipFree(d);
-    for (void *h : {(void *)s->h_seg_start[b], (void *)s->h_seg_curve[b],
-                    (void *)s->h_seg_tile0[b]})
-      if (h) (void)hipHostFree(h);
+    if (s->h_seg[b]) (void)hipHostFree(s->h_seg[b]);
     if (s->ev_s[b]) (void)hipEventDestroy(s->ev_s[b]);
     if (s->ev_e[b]) (void)hipEventDestroy(s->ev_e[b]);
   }
