@@ -99,7 +99,11 @@ struct bls_server {
   int device = 0;
   int num_cus = 0;
   int max_lds = 0;
-  hipStream_t stream = nullptr, copy_stream = nullptr;
+  // stream: the ticks; up_stream: admitted requests' uploads and prep, which
+  // the next tick waits for (ev_up); copy_stream: result copies
+  hipStream_t stream = nullptr, copy_stream = nullptr, up_stream = nullptr;
+  hipEvent_t ev_up = nullptr;
+  bool up_pending = false;
 
   int64_t cap_pts = 0, cap_per = 0;
   int64_t arena_budget = 0;   // bytes of resident requests allowed at once
@@ -183,7 +187,8 @@ void fail_all(bls_server *s, int st) {
   s->cv_done.notify_all();
 }
 
-// Device work for a newly admitted request: inputs, descriptor, prep, key.
+// Device work for a newly admitted request: inputs, descriptor, prep, key,
+// on the upload stream (they overlap the ticks in flight).
 hipError_t start_request(bls_server *s, Req *r) {
   CurveDesc &d = s->h_curves[r->slot];
   memset(&d, 0, sizeof d);
@@ -202,7 +207,7 @@ hipError_t start_request(bls_server *s, Req *r) {
   d.qbits = std::min(kQBitsMax, 63 - 2 * cb);
   d.weighted = r->weighted ? 1 : 0;
   d.check_periods = 0;  // checked on the host at submit
-  hipStream_t st = s->stream;
+  hipStream_t st = s->up_stream;
   hipError_t e;
   const size_t n = (size_t)r->n, np = (size_t)r->np;
   if (r->pin_off != Arena::kFail) {
@@ -550,6 +555,16 @@ void scheduler(bls_server *s) {
       hipError_t e = hipSuccess;
       for (Req *r : admitted)
         if (e == hipSuccess) e = start_request(s, r);
+      if (e == hipSuccess && !admitted.empty()) {
+        e = hipEventRecord(s->ev_up, s->up_stream);
+        s->up_pending = true;
+      }
+      // a tick holds tiles of every admitted request: it starts after their
+      // uploads and prep
+      if (e == hipSuccess && have_tick && s->up_pending) {
+        e = hipStreamWaitEvent(s->stream, s->ev_up, 0);
+        s->up_pending = false;
+      }
       if (e == hipSuccess && have_tick) e = launch_tick(s, tk);
       lk.lock();
       if (e != hipSuccess) {
@@ -635,7 +650,9 @@ int bls_server_create(bls_server **out, const bls_server_config *cfg_in) {
   s->num_cus = prop.multiProcessorCount;
   s->max_lds = (int)prop.sharedMemPerBlock;
   if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) ||
-      (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)))
+      (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)) ||
+      (e = hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking)) ||
+      (e = hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming)))
     return fail(srv_hip(s, e, "create streams"));
 
   // Arena: point arrays and period arrays in two address ranges, each able
@@ -950,6 +967,7 @@ int bls_server_destroy(bls_server *s) {
   }
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+  if (s->up_stream) (void)hipStreamSynchronize(s->up_stream);
   for (void *d : {s->d_txw, (void *)s->d_dt,
                   (void *)s->d_q, (void *)s->d_qw, (void *)s->d_per, s->d_res,
                   (void *)s->d_curves, (void *)s->d_keys})
@@ -969,6 +987,8 @@ int bls_server_destroy(bls_server *s) {
   if (s->h_res) (void)hipHostFree(s->h_res);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  if (s->up_stream) (void)hipStreamDestroy(s->up_stream);
+  if (s->ev_up) (void)hipEventDestroy(s->ev_up);
   delete s;
   return BLS_OK;
 }
