@@ -655,6 +655,7 @@ def suite_unbinned(args, bls):
         st = bls.bls_last_stats(p.handle)
     k_ms = _median(kms[1:])
     pp, steps = st["trial_points"], st["box_evals"]
+    long_rec = _unbinned_long_curves(args, bls)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -673,7 +674,48 @@ def suite_unbinned(args, bls):
                        "work_items": st["work_items"]},
             "roofline": _alu_roofline(SLOTS_UNBINNED_PP * pp +
                                       SLOTS_UNBINNED_STEP * steps, k_ms),
+            "long_curves": long_rec,
             "cpu_baseline": cpu}
+
+
+def _unbinned_long_curves(args, bls):
+    """Unbinned search of curves too long for LDS (their per-point arrays in
+    the device workspace): 4 curves of 20000 points, 2000 periods."""
+    import numpy as np
+    import torch
+
+    import synth
+    log("suite unbinned long curves")
+    ncur, n = 4, 20000
+    lcs = [synth.small_curve(7100 + k, n, nperiods=2000, nbins=64, qmin=0.01,
+                             qmax=0.1) for k in range(ncur)]
+    n_off = np.arange(0, (ncur + 1) * n, n, dtype=np.int64)
+    dev = torch.device("cuda:0")
+    t = torch.tensor(np.concatenate([lc.t for lc in lcs]), device=dev)
+    x = torch.tensor(np.concatenate([lc.x for lc in lcs]), device=dev)
+    per = torch.tensor(lcs[0].periods, device=dev)
+    mres = ncur * lcs[0].periods.size
+    outs = [torch.empty(mres, device=dev, dtype=torch.float32),
+            torch.empty(mres, device=dev, dtype=torch.float32),
+            torch.empty(mres, device=dev, dtype=torch.int32),
+            torch.empty(mres, device=dev, dtype=torch.int32),
+            torch.empty(ncur, device=dev, dtype=torch.int64)]
+    with bls.Plan(max_curves=ncur, max_points=int(n_off[-1]),
+                  max_periods=mres) as p:
+        kms = []
+        for r in range(args.suite_steps + 1):
+            bls.bls_search_unbinned_device(p.handle, n_off, t, x, None, per,
+                                           None, 0.01, 0.1, *outs)
+            bls.bls_synchronize(p.handle)
+            kms.append(bls.bls_last_stats(p.handle)["search_ms"])
+        st = bls.bls_last_stats(p.handle)
+    k_ms = _median(kms[1:])
+    return {"workload": "4 x N=20000 (device-workspace path), 2000 log "
+                        "periods, q 0.01-0.10",
+            "kernel_ms": k_ms,
+            "trial_points_per_s": st["trial_points"] / (k_ms * 1e-3),
+            "run_steps_est": st["box_evals"],
+            "launch": {"grid": st["grid"], "work_items": st["work_items"]}}
 
 
 def suite_detect(args, bls):
