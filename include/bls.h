@@ -531,7 +531,10 @@ typedef struct {
 } bls_request;
 
 /* A finished request.  The arrays belong to the server and stay valid
- * until bls_server_release(ticket). */
+ * until bls_server_release(ticket).  They sit in the server's pinned result
+ * pool when it had room for them (pageable memory otherwise, which costs
+ * the scheduler a wait per request): releasing finished requests promptly
+ * keeps later ones in the pool. */
 typedef struct {
     int32_t status;               /* BLS_OK or the request's error             */
     int32_t reserved;
@@ -561,8 +564,12 @@ typedef struct {
  * 1, no flags, automatic tick size, N <= 2^20, nperiods <= 2^20. */
 void bls_server_config_init(bls_server_config *cfg);
 
-/* Allocate the arena and start the scheduler thread.  Errors: INVALID_ARG,
- * NO_MEMORY, DEVICE (message via bls_server_last_error(NULL, ...)). */
+/* Allocate the arena and start the scheduler thread.  Besides the device
+ * arena the server pins host memory: a quarter of arena_bytes (at most 1 GiB)
+ * to stage request inputs and half (at most 2 GiB) for finished requests'
+ * results; where pinning fails it works from pageable memory.  Errors:
+ * INVALID_ARG, NO_MEMORY, DEVICE (message via bls_server_last_error(NULL,
+ * ...)). */
 int bls_server_create(bls_server **out, const bls_server_config *cfg);
 
 /* Queue a request; non-blocking; inputs are copied.  *ticket identifies it.

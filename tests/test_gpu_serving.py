@@ -190,3 +190,40 @@ def test_open_loop_stream_reports_latency(bls):
     assert 0 < st["p50_ms"] <= st["p99_ms"]
     assert st["trial_points"] == pytest.approx(
         sum(lc.n * lc.periods.size for _, lc in reqs))
+
+
+def test_result_pool_reuse_and_fallback(bls):
+    """Finished requests hold blocks of the pinned result pool (half the
+    arena) until released; a request finding no room gets its results
+    copied into pageable memory instead.  With a 1 MiB arena the 512 KiB pool
+    holds one of these requests' results at a time, so in each wave of three
+    the first lands in the pool and the other two take the pageable path;
+    releasing between waves lets the pool be reused.  Every result must be
+    bit-identical to the same request searched alone."""
+    reqs = _requests(9, 5353, n_range=(300, 800), np_range=(18000, 21000),
+                     nbins_range=(100, 200), weighted_every=4)
+    assert all(16 * lc.periods.size + 16 > (1 << 20) // 4 for lc in reqs)
+    _say("result pool", len(reqs))
+    srv = bls.bls_server_create(max_slots=4, arena_bytes=1 << 20)
+    res = []
+    try:
+        for w in range(0, len(reqs), 3):
+            tickets = [_submit(bls, srv, lc) for lc in reqs[w:w + 3]]
+            res += [bls.bls_server_wait(srv, tk, 60.0) for tk in tickets]
+            for tk in tickets:
+                bls.bls_server_release(srv, tk)
+        st = bls.bls_server_get_stats(srv)
+    finally:
+        bls.bls_server_destroy(srv)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    with bls.Plan(max_points=1 << 12, max_periods=1 << 15) as p:
+        for k, (lc, r) in enumerate(zip(reqs, res)):
+            assert r["status"] == bls.BLS_OK, k
+            alone = bls.bls_search(p.handle, lc.t, lc.x, lc.w, lc.periods,
+                                   lc.nbins, lc.qmin, lc.qmax)
+            assert np.array_equal(alone["sr"].astype(np.float32), r["sr"]), k
+            assert np.array_equal(alone["depth"].astype(np.float32),
+                                  r["depth"], equal_nan=True), k
+            assert np.array_equal(alone["jstart"], r["jstart"]), k
+            assert np.array_equal(alone["kwidth"], r["kwidth"]), k
+            assert alone["best_index"] == r["best_index"], k
