@@ -122,14 +122,6 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   auto key_index = [](unsigned long long key) -> int64_t {
     return (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
   };
-  double tper[kDetList];
-  unsigned dead = 0u;  // bit i: entry i empty, taken or suppressed
-#pragma unroll
-  for (int i = 0; i < kDetList; ++i) {
-    tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
-    if (!top[i]) dead |= 1u << i;
-  }
-  bool more = npos > kDetList;  // the slice holds values the list dropped
   const double harm[5] = {1.0, 0.5, 2.0, 1.0 / 3.0, 3.0};
   auto suppressed = [&](double Pp, double P) {
     bool off = false;
@@ -139,10 +131,42 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
     }
     return off;
   };
+  // A thread offers its largest entry that is neither taken nor suppressed
+  // by a peak so far.  The entries' periods are read lazily: only the
+  // current entry's (top[0]), tested against the peaks it has not met yet
+  // when it is about to be offered.  Read for all entries at once, the
+  // periods cost more than twice the pass (random reads that together touch
+  // nearly every line of the period grid in every workgroup); most entries
+  // are never offered.  An entry that is taken or suppressed is popped and
+  // the next one becomes current; the next entry's period is read one pop
+  // ahead, so that a pop does not wait on memory.
+  double curP = top[0] ? per[key_index(top[0])] : 0.0;
+  double nextP = top[1] ? per[key_index(top[1])] : 0.0;
+  auto pop = [&]() {
+#pragma unroll
+    for (int i = 0; i + 1 < kDetList; ++i) top[i] = top[i + 1];
+    top[kDetList - 1] = 0ull;
+    curP = nextP;
+    nextP = top[1] ? per[key_index(top[1])] : 0.0;
+  };
+  int tested = 0;               // peaks the current entry has been tested against
+  bool more = npos > kDetList;  // the slice holds values the list dropped
 
   int k = 0;
   for (; k < a.max_peaks; ++k) {
-    if (dead == (1u << kDetList) - 1u && more) {
+    // The current entry against the peaks it has not met; suppressed ones
+    // give way to the next.
+    while (top[0] != 0ull && tested < k) {
+      bool off = false;
+      for (int j = tested; j < k; ++j) off = off || suppressed(curP, s_peak[j]);
+      if (!off) {
+        tested = k;
+        break;
+      }
+      pop();
+      tested = 0;
+    }
+    if (top[0] == 0ull && more) {
       // Refill the list with the slice's largest entries free of every peak
       // so far.  Only a value that would enter the list is tested; one that
       // would not, or one pushed out, leaves `more` set (a later refill
@@ -187,21 +211,11 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
         for (int u = 0; u < kDetRefill; ++u) retake(v[u], pp[u], q0 + (int64_t)u * kBlock);
       }
       for (int64_t q = q0; q < m; q += kBlock) retake(sr[q], per[q], q);
-      dead = 0u;
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i) {
-        tper[i] = top[i] ? per[key_index(top[i])] : 0.0;
-        if (!top[i]) dead |= 1u << i;
-      }
+      curP = top[0] ? per[key_index(top[0])] : 0.0;
+      nextP = top[1] ? per[key_index(top[1])] : 0.0;
+      tested = k;  // the refill tested its entries against every peak so far
     }
-    unsigned long long offer = 0ull;
-    int mine = -1;
-#pragma unroll
-    for (int i = kDetList - 1; i >= 0; --i)
-      if (!((dead >> i) & 1u)) {
-        offer = top[i];
-        mine = i;
-      }
+    const unsigned long long offer = top[0];
     // Largest offer: across the wave by shuffles, across the waves in LDS.
     // (Every read of s_key for the previous peak happened before the barrier
     // that published that peak's period.)
@@ -217,13 +231,9 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
 #pragma unroll
     for (int w = 1; w < kBlock / 64; ++w) key = s_key[w] > key ? s_key[w] : key;
     if (key == 0ull) break;
-    if (offer == key) {  // the owner: its entry's period for everyone
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i)
-        if (i == mine) s_peak[k] = tper[i];
-    }
+    const bool mine = offer == key;  // keys are unique: one owner
+    if (mine) s_peak[k] = curP;
     __syncthreads();
-    const double P = s_peak[k];
     const int64_t pk = key_index(key);
     const float vk = __uint_as_float((unsigned)(key >> 32));
     if (tid == 0) {
@@ -231,15 +241,9 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
       out->peak_sr[k] = vk;
       out->peak_sde[k] = sd > 0.0 ? (float)(((double)vk - mean) / sd) : 0.0f;
     }
-    // The suppression test of every entry, harmonic by harmonic (the same
-    // products as the refill's test, so the two agree bit for bit).
-#pragma unroll
-    for (int h = 0; h < 5; ++h) {
-      const double cp = harm[h] * P;
-      const double wc = a.window * cp;
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i)
-        if (fabs(tper[i] - cp) <= wc) dead |= 1u << i;
+    if (mine) {  // the owner's entry is taken
+      pop();
+      tested = 0;
     }
   }
   if (tid == 0) {
