@@ -17,23 +17,26 @@ namespace {
 // peaks largest first, a peak at P suppressing every P' within
 // window * hP of hP for h in {1, 1/2, 2, 1/3, 3}.
 //
-// Peaks without a pass per peak: while the deviation pass reads SR, every
-// thread keeps the kDetList largest keys of its slice of periods (p = tid +
-// kBlock j, positive SR only) with their periods.  A key is (SR bits, ~p),
-// unique, and orders periods as the peaks are chosen (larger SR, then the
-// smaller index).  For each peak a thread offers its largest entry not yet
-// suppressed, the workgroup takes the largest offer, and every thread tests
-// its remaining entries against the new peak.  A thread whose entries are all
-// used up while its slice holds more positive values scans its slice again
-// against every peak so far and refills its list.
-// List length: each entry costs four VGPRs and insertion work in the
-// deviation pass; too short a list runs out near strong peaks and their
-// harmonics, and a refill re-reads the slice.  On 20000-period periodograms
-// of 2000-point curves, 12 is fastest for 8 peaks (8: refills set the
-// kernel's tail; 16: the pass loses occupancy).
-constexpr int kDetList = 12;
-constexpr int kDetBatch = 8;   // loads in flight per pass
-constexpr int kDetRefill = 4;  // loads in flight per refill (registers)
+// Peaks without a pass per peak.  The deviation pass reads a thread's slice
+// of periods (p = tid + kBlock j) kDetBatch values at a time, and batch lane
+// u keeps a bucket: the two largest keys among the slice's values with
+// j = u (mod kDetBatch), positive SR only.  A key is (SR bits, ~p): unique,
+// and ordered as the peaks are chosen (larger SR, then the smaller index).
+// A thread's current entry is its largest bucket key; before it is offered
+// it is tested against the peaks it has not met (its period is read then).
+// The workgroup takes the largest offer.  An entry that is taken or
+// suppressed leaves its bucket, whose next key is its second, or, once that
+// is used up, the largest one below it, found (with the one after) by
+// rescanning the bucket's values (every kDetBatch-th of the slice).  A
+// thread so always offers the largest free key of its slice, and the peaks
+// are exactly those of a peak-by-peak search.  In the pass a bucket costs a
+// compare or two per value; the sorted list of 12 keys this replaces cost a
+// 12-step chain per inserted value, about 34 of a 78-value slice, which was
+// most of the kernel's time.  (Buckets of one key rescan twice as often;
+// three or four keys, or 16 or 32 buckets, cost more in registers than they
+// save.)
+constexpr int kDetBatch = 8;   // loads in flight per pass; buckets per thread
+constexpr int kDetRescan = 4;  // loads in flight per bucket rescan
 
 __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   __shared__ double sa[kBlock];
@@ -54,28 +57,29 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
   // (whole batches, then the tail) and keeps: the running count, mean and sum
   // of squared deviations of its values, each batch merged in by the pairwise
   // update of Chan, Golub and LeVeque (one value at a time in the tail); its
-  // largest value; and its list (descending keys).  The workgroup merges the
-  // threads' statistics the same way, in a fixed tree.
-  unsigned long long top[kDetList];
+  // largest value; and its buckets.  The workgroup merges the threads'
+  // statistics the same way, in a fixed tree.
+  auto keyof = [](float v, int64_t p) {
+    return ((unsigned long long)__float_as_uint(v) << 32) |
+           (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
+  };
+  // bkey[u]: the bucket's largest key; bkey2[u]: the next one below it (0:
+  // none known, found by a rescan when needed)
+  unsigned long long bkey[kDetBatch], bkey2[kDetBatch];
 #pragma unroll
-  for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
-  int npos = 0;  // positive SR values in this thread's slice
+  for (int u = 0; u < kDetBatch; ++u) {
+    bkey[u] = 0ull;
+    bkey2[u] = 0ull;
+  }
   double cn = 0.0, cmean = 0.0, cm2 = 0.0, mx = -INFINITY;
-  auto take = [&](float v, int64_t p) {
+  auto take = [&](int u, float v, int64_t p) {
     mx = fmax(mx, (double)v);
     if (v > 0.0f) {
-      ++npos;
-      unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                               (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-      if (key > top[kDetList - 1]) {
-#pragma unroll
-        for (int i = 0; i < kDetList; ++i) {
-          if (key > top[i]) {
-            const unsigned long long o = top[i];
-            top[i] = key;
-            key = o;
-          }
-        }
+      const unsigned long long key = keyof(v, p);
+      if (key > bkey2[u]) {
+        const bool top = key > bkey[u];
+        bkey2[u] = top ? bkey[u] : key;
+        bkey[u] = top ? key : bkey[u];
       }
     }
   };
@@ -102,15 +106,20 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
     cm2 = cm2 + bm2 + delta * delta * cn * fb;
     cn = nn;
 #pragma unroll
-    for (int u = 0; u < kDetBatch; ++u) take(v[u], p0 + (int64_t)u * kBlock);
+    for (int u = 0; u < kDetBatch; ++u) take(u, v[u], p0 + (int64_t)u * kBlock);
   }
-  for (int64_t p = p0; p < m; p += kBlock) {
-    const float v = sr[p];
-    cn = cn + 1.0;
-    const double delta = (double)v - cmean;
-    cmean = cmean + delta / cn;
-    cm2 = cm2 + delta * ((double)v - cmean);
-    take(v, p);
+  // the tail: fewer than kDetBatch values, lane u's in bucket u
+#pragma unroll
+  for (int u = 0; u < kDetBatch - 1; ++u) {
+    const int64_t p = p0 + (int64_t)u * kBlock;
+    if (p < m) {
+      const float v = sr[p];
+      cn = cn + 1.0;
+      const double delta = (double)v - cmean;
+      cmean = cmean + delta / cn;
+      cm2 = cm2 + delta * ((double)v - cmean);
+      take(u, v, p);
+    }
   }
   block_chan(cn, cmean, cm2, sa, sb, sc);
   double mn = INFINITY;
@@ -131,32 +140,70 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
     }
     return off;
   };
-  // A thread offers its largest entry that is neither taken nor suppressed
-  // by a peak so far.  The entries' periods are read lazily: only the
-  // current entry's (top[0]), tested against the peaks it has not met yet
-  // when it is about to be offered.  Read for all entries at once, the
-  // periods cost more than twice the pass (random reads that together touch
-  // nearly every line of the period grid in every workgroup); most entries
-  // are never offered.  An entry that is taken or suppressed is popped and
-  // the next one becomes current; the next entry's period is read one pop
-  // ahead, so that a pop does not wait on memory.
-  double curP = top[0] ? per[key_index(top[0])] : 0.0;
-  double nextP = top[1] ? per[key_index(top[1])] : 0.0;
-  auto pop = [&]() {
+  // The two largest keys below `bound` among bucket u's values (0: none).
+  auto rescan = [&](int u, unsigned long long bound, unsigned long long &best,
+                    unsigned long long &second) {
+    const int64_t step = (int64_t)kDetBatch * kBlock;
+    best = 0ull;
+    second = 0ull;
+    auto see = [&](float v, int64_t p) {
+      if (v > 0.0f) {
+        const unsigned long long key = keyof(v, p);
+        if (key < bound && key > second) {
+          const bool top = key > best;
+          second = top ? best : key;
+          best = top ? key : best;
+        }
+      }
+    };
+    int64_t q = tid + (int64_t)u * kBlock;
+    for (; q + (kDetRescan - 1) * step < m; q += kDetRescan * step) {
+      float v[kDetRescan];
 #pragma unroll
-    for (int i = 0; i + 1 < kDetList; ++i) top[i] = top[i + 1];
-    top[kDetList - 1] = 0ull;
-    curP = nextP;
-    nextP = top[1] ? per[key_index(top[1])] : 0.0;
+      for (int r = 0; r < kDetRescan; ++r) v[r] = sr[q + r * step];
+#pragma unroll
+      for (int r = 0; r < kDetRescan; ++r) see(v[r], q + r * step);
+    }
+    for (; q < m; q += step) see(sr[q], q);
   };
-  int tested = 0;               // peaks the current entry has been tested against
-  bool more = npos > kDetList;  // the slice holds values the list dropped
+  // The current entry: the largest bucket key, its bucket and period, and
+  // how many peaks it has been tested against.
+  unsigned long long ckey = 0ull;
+  int cu = 0, tested = 0;
+  double curP = 0.0;
+  auto pick = [&]() {
+    ckey = 0ull;
+    cu = 0;
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u)
+      if (bkey[u] > ckey) {
+        ckey = bkey[u];
+        cu = u;
+      }
+    curP = ckey ? per[key_index(ckey)] : 0.0;
+    tested = 0;
+  };
+  auto pop = [&]() {  // the current entry leaves its bucket
+    unsigned long long b1 = 0ull, b2 = 0ull;
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u)
+      if (u == cu) b1 = bkey2[u];
+    if (b1 == 0ull) rescan(cu, ckey, b1, b2);  // the next key is not known
+#pragma unroll
+    for (int u = 0; u < kDetBatch; ++u)
+      if (u == cu) {
+        bkey[u] = b1;
+        bkey2[u] = b2;
+      }
+    pick();
+  };
+  pick();
 
   int k = 0;
   for (; k < a.max_peaks; ++k) {
-    // The current entry against the peaks it has not met; suppressed ones
-    // give way to the next.
-    while (top[0] != 0ull && tested < k) {
+    // The current entry against the peaks it has not met; a suppressed one
+    // gives way to the next.
+    while (ckey != 0ull && tested < k) {
       bool off = false;
       for (int j = tested; j < k; ++j) off = off || suppressed(curP, s_peak[j]);
       if (!off) {
@@ -164,58 +211,8 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
         break;
       }
       pop();
-      tested = 0;
     }
-    if (top[0] == 0ull && more) {
-      // Refill the list with the slice's largest entries free of every peak
-      // so far.  Only a value that would enter the list is tested; one that
-      // would not, or one pushed out, leaves `more` set (a later refill
-      // tests it then).
-#pragma unroll
-      for (int i = 0; i < kDetList; ++i) top[i] = 0ull;
-      more = false;
-      auto retake = [&](float v, double Pp, int64_t p) {
-        if (!(v > 0.0f)) return;
-        unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) |
-                                 (unsigned long long)(0xFFFFFFFFu - (unsigned)p);
-        if (key < top[kDetList - 1]) {
-          more = true;
-          return;
-        }
-        bool off = false;
-        for (int j = 0; j < k; ++j) off = off || suppressed(Pp, s_peak[j]);
-        if (off) return;
-        if (top[kDetList - 1]) more = true;  // the last entry drops out
-#pragma unroll
-        for (int i = 0; i < kDetList; ++i) {
-          if (key > top[i]) {
-            const unsigned long long o = top[i];
-            top[i] = key;
-            key = o;
-          }
-        }
-      };
-      // Loads in batches, as in the passes above: a refill is a chain of
-      // dependent loads otherwise.
-      const int64_t rfull = m - (int64_t)(kDetRefill - 1) * kBlock;
-      int64_t q0 = tid;
-      for (; q0 < rfull; q0 += kDetRefill * kBlock) {
-        float v[kDetRefill];
-        double pp[kDetRefill];
-#pragma unroll
-        for (int u = 0; u < kDetRefill; ++u) {
-          v[u] = sr[q0 + (int64_t)u * kBlock];
-          pp[u] = per[q0 + (int64_t)u * kBlock];
-        }
-#pragma unroll
-        for (int u = 0; u < kDetRefill; ++u) retake(v[u], pp[u], q0 + (int64_t)u * kBlock);
-      }
-      for (int64_t q = q0; q < m; q += kBlock) retake(sr[q], per[q], q);
-      curP = top[0] ? per[key_index(top[0])] : 0.0;
-      nextP = top[1] ? per[key_index(top[1])] : 0.0;
-      tested = k;  // the refill tested its entries against every peak so far
-    }
-    const unsigned long long offer = top[0];
+    const unsigned long long offer = ckey;
     // Largest offer: across the wave by shuffles, across the waves in LDS.
     // (Every read of s_key for the previous peak happened before the barrier
     // that published that peak's period.)
@@ -241,10 +238,7 @@ __global__ __launch_bounds__(kBlock) void detect_kernel(DetectArgs a) {
       out->peak_sr[k] = vk;
       out->peak_sde[k] = sd > 0.0 ? (float)(((double)vk - mean) / sd) : 0.0f;
     }
-    if (mine) {  // the owner's entry is taken
-      pop();
-      tested = 0;
-    }
+    if (mine) pop();  // the owner's entry is taken
   }
   if (tid == 0) {
     out->mean_sr = mean;
