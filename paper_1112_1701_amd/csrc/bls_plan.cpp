@@ -17,6 +17,7 @@
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 namespace bls {
@@ -773,6 +774,54 @@ namespace {
 // reached its end event); 0 if there is none.
 // Host-array search of a validated batch (shared by bls_search and
 // bls_search_batch).
+// f(i0, i1) over [0, n) in contiguous pieces on up to 16 host threads, one
+// piece per `grain` items at least (the calling thread takes the last).
+template <class F>
+void par_ranges(int64_t n, int64_t grain, F f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t nt = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)std::min(hw, 16u), n / std::max<int64_t>(grain, 1)));
+  std::vector<std::thread> th;
+  int64_t i0 = 0;
+  for (int64_t t = 0; t + 1 < nt; ++t) {
+    const int64_t i1 = n * (t + 1) / nt;
+    try {
+      th.emplace_back(f, i0, i1);
+    } catch (...) {
+      f(i0, i1);  // no thread: this one does the piece
+    }
+    i0 = i1;
+  }
+  f(i0, n);
+  for (auto &x : th) x.join();
+}
+
+// Copy of `bytes` between host buffers on several threads (a single thread
+// copies at a fraction of the memory bandwidth).
+void par_copy(void *dst, const void *src, size_t bytes) {
+  par_ranges((int64_t)bytes, int64_t(8) << 20, [&](int64_t i0, int64_t i1) {
+    memcpy((char *)dst + i0, (const char *)src + i0, (size_t)(i1 - i0));
+  });
+}
+
+// Pinned staging for the host API, sized once for the plan's limits: the
+// inputs (times, flux, weights, periods) or the results (SR, depth, first
+// and last bin, best index), whichever is larger.  False if pinned memory
+// is not available (the host API then copies from pageable memory).
+bool ensure_host_stage(bls_plan *p) {
+  if (p->h_stage) return true;
+  const size_t np = (size_t)p->cfg.max_points, nr = (size_t)p->cfg.max_periods,
+               nc = (size_t)p->cfg.max_curves;
+  const size_t in = 3 * np * 8 + nr * 8 + 256, res = 4 * nr * 4 + nc * 8 + 256;
+  const size_t bytes = std::max(in, res);
+  if (hipHostMalloc((void **)&p->h_stage, bytes, 0) != hipSuccess) {
+    p->h_stage = nullptr;
+    return false;
+  }
+  p->h_stage_bytes = bytes;
+  return true;
+}
+
 int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &shapes,
                 const bls_results &out) {
   int st = ensure_staging(p);
@@ -788,15 +837,32 @@ int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &
   const int64_t nper = b.p_off ? b.p_off[b.ncurves] : b.nperiods_shared;
   hipStream_t s = p->stream;
   hipError_t e;
+  // Inputs through the pinned staging when there is one: a threaded copy
+  // into it, then DMA (pageable copies run at a fraction of that rate).  The
+  // previous call's copies from or into it ended with that call.
+  const bool pinned = ensure_host_stage(p);
+  const double *src_t = b.times, *src_x = b.flux, *src_w = b.weights, *src_p = b.periods;
+  if (pinned) {
+    double *st = reinterpret_cast<double *>(p->h_stage);
+    double *sx = st + npts, *sw = sx + npts, *sp = sw + (weighted ? npts : 0);
+    par_copy(st, b.times, (size_t)npts * 8);
+    par_copy(sx, b.flux, (size_t)npts * 8);
+    if (weighted) par_copy(sw, b.weights, (size_t)npts * 8);
+    par_copy(sp, b.periods, (size_t)nper * 8);
+    src_t = st;
+    src_x = sx;
+    src_w = weighted ? sw : nullptr;
+    src_p = sp;
+  }
   if ((e = hipEventRecord(p->ev_begin, s)) != hipSuccess) return hip_error(p, e, "event");
-  if ((e = hipMemcpyAsync(p->d_t, b.times, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+  if ((e = hipMemcpyAsync(p->d_t, src_t, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_error(p, e, "upload times");
-  if ((e = hipMemcpyAsync(p->d_x, b.flux, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+  if ((e = hipMemcpyAsync(p->d_x, src_x, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_error(p, e, "upload flux");
   if (weighted &&
-      (e = hipMemcpyAsync(p->d_w, b.weights, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+      (e = hipMemcpyAsync(p->d_w, src_w, npts * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_error(p, e, "upload weights");
-  if ((e = hipMemcpyAsync(p->d_periods, b.periods, nper * 8, hipMemcpyHostToDevice, s)) !=
+  if ((e = hipMemcpyAsync(p->d_periods, src_p, nper * 8, hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return hip_error(p, e, "upload periods");
   st = enqueue_search(p, pb, p->d_t, p->d_x, weighted ? p->d_w : nullptr, p->d_periods, p->d_sr,
@@ -804,16 +870,38 @@ int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &
   if (st != BLS_OK) return st;
   if ((e = hipEventRecord(p->ev_end, s)) != hipSuccess) return hip_error(p, e, "event");
 
+  // Results into the pinned staging (the uploads from it have run by then:
+  // same stream), else into pageable vectors.
   const int64_t nres = pb.total_results;
-  std::vector<float> sr(nres), depth(nres);
-  std::vector<int32_t> js(nres), ks(nres);
-  std::vector<int64_t> best(b.ncurves);
-  if ((e = hipMemcpyAsync(sr.data(), p->d_sr, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(depth.data(), p->d_depth, nres * 4, hipMemcpyDeviceToHost, s)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(js.data(), p->d_j, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(ks.data(), p->d_k, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(best.data(), p->d_best, b.ncurves * 8, hipMemcpyDeviceToHost, s)) !=
+  std::vector<float> v_sr, v_depth;
+  std::vector<int32_t> v_js, v_ks;
+  std::vector<int64_t> v_best;
+  float *sr, *depth;
+  int32_t *js, *ks;
+  int64_t *best;
+  if (pinned) {
+    best = reinterpret_cast<int64_t *>(p->h_stage);
+    sr = reinterpret_cast<float *>(best + b.ncurves);
+    depth = sr + nres;
+    js = reinterpret_cast<int32_t *>(depth + nres);
+    ks = js + nres;
+  } else {
+    v_sr.resize(nres);
+    v_depth.resize(nres);
+    v_js.resize(nres);
+    v_ks.resize(nres);
+    v_best.resize(b.ncurves);
+    sr = v_sr.data();
+    depth = v_depth.data();
+    js = v_js.data();
+    ks = v_ks.data();
+    best = v_best.data();
+  }
+  if ((e = hipMemcpyAsync(sr, p->d_sr, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(depth, p->d_depth, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(js, p->d_j, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(ks, p->d_k, nres * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(best, p->d_best, b.ncurves * 8, hipMemcpyDeviceToHost, s)) !=
           hipSuccess)
     return hip_error(p, e, "download results");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(p, e, "search");
@@ -827,21 +915,27 @@ int host_search(bls_plan *p, const bls_batch &b, const std::vector<CurveShape> &
   fill_stats(p, pb, false);
 
   // Results: (value, box) per period at r_off; phase and duration from j, k.
-  for (int c = 0; c < b.ncurves; ++c) {
-    const CurveShape &cs = shapes[c];
-    const double *per = b.periods + cs.p_off;
-    for (int32_t i = 0; i < cs.nperiods; ++i) {
-      const int64_t r = cs.r_off + i;
-      const bool none = ks[r] < 0;
-      if (out.sr) out.sr[r] = (double)sr[r];
-      if (out.depth) out.depth[r] = none ? NAN : (double)depth[r];
-      if (out.jstart) out.jstart[r] = js[r];
-      if (out.kwidth) out.kwidth[r] = ks[r];
-      if (out.phase) out.phase[r] = none ? NAN : (double)js[r] / (double)cs.nbins;
-      if (out.duration) out.duration[r] = none ? NAN : (double)ks[r] * per[i] / (double)cs.nbins;
+  // Up to 40 B are written per result: host threads take contiguous curve
+  // ranges.
+  par_ranges(b.ncurves, std::max<int64_t>(1, (int64_t)b.ncurves * (int64_t(1) << 20) /
+                                                 std::max<int64_t>(nres, 1)),
+             [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      const CurveShape &cs = shapes[c];
+      const double *per = b.periods + cs.p_off;
+      for (int32_t i = 0; i < cs.nperiods; ++i) {
+        const int64_t r = cs.r_off + i;
+        const bool none = ks[r] < 0;
+        if (out.sr) out.sr[r] = (double)sr[r];
+        if (out.depth) out.depth[r] = none ? NAN : (double)depth[r];
+        if (out.jstart) out.jstart[r] = js[r];
+        if (out.kwidth) out.kwidth[r] = ks[r];
+        if (out.phase) out.phase[r] = none ? NAN : (double)js[r] / (double)cs.nbins;
+        if (out.duration) out.duration[r] = none ? NAN : (double)ks[r] * per[i] / (double)cs.nbins;
+      }
+      if (out.best_index) out.best_index[c] = best[c];
     }
-    if (out.best_index) out.best_index[c] = best[c];
-  }
+  });
   p->last = pb;
   return BLS_OK;
 }
@@ -1024,7 +1118,7 @@ int bls_plan_destroy(bls_plan *p) {
                   (void *)p->d_k, (void *)p->d_best})
     free_dev(d);
   for (void *h : {(void *)p->h_curves, (void *)p->h_seg_start, (void *)p->h_seg_curve,
-                  (void *)p->h_seg_tile0})
+                  (void *)p->h_seg_tile0, (void *)p->h_stage})
     if (h) (void)hipHostFree(h);
   for (hipEvent_t ev : {p->ev_begin, p->ev_search0, p->ev_search1, p->ev_end, p->ev_desc})
     if (ev) (void)hipEventDestroy(ev);

@@ -71,6 +71,10 @@ struct bls_plan {
   float *d_sr = nullptr, *d_depth = nullptr;
   int32_t *d_j = nullptr, *d_k = nullptr;
   int64_t *d_best = nullptr;
+  // pinned host staging of the host API (allocated on first use): a call's
+  // inputs on the way in, its results on the way out
+  char *h_stage = nullptr;
+  size_t h_stage_bytes = 0;
 
   // detection buffers (allocated on first use)
   bls::DetectDesc *d_detect_desc = nullptr;
