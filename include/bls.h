@@ -101,7 +101,11 @@ int bls_plan_destroy(bls_plan *plan);
  * Outputs, [nperiods] each, caller-owned, any may be NULL: sr, phase,
  * duration, depth (doubles), jstart, kwidth (box start bin and width);
  * best_index: first period index with the largest SR (may be NULL).
- * Synchronous.  On any error the outputs are untouched.
+ * Synchronous.  On any error the outputs are untouched.  The first host-array
+ * call on a plan pins a host staging buffer sized for the plan's limits
+ * (24 B per point plus 8 B per result, or 16 B per result, the larger),
+ * kept until bls_plan_destroy; without pinned memory the copies run from
+ * the caller's pageable arrays.
  * Errors: INVALID_ARG (non-finite time or flux of a kept point, negative or
  * non-finite weight, fewer than 2 kept points, bad period, nbins or q range,
  * kmin > kmax), CAPACITY (n, nperiods or nbins above the plan's limits),
