@@ -381,13 +381,14 @@ def detection_periodograms(seed: int = _BASE_SEED + 9):
     rng = np.random.default_rng(seed)
     cases = []
     # The 24 largest values all in one 256-stride slice (indices 3 mod 256):
-    # more than a thread keeps of its slice, so 16 peaks force a refill.
+    # more than a thread keeps of its slice at once, so 16 peaks make it
+    # look again (its buckets are rescanned).
     m = 256 * 30 + 17
     sr = rng.uniform(0.0, 1.0, m)
     sr[3 + 256 * np.arange(24)] = 2.0 + rng.uniform(0.0, 1.0, 24)
     cases.append((sr, np.geomspace(1.0, 40.0, m), 16, 1e-6))
     # Same slice, but its peaks are wiped out by harmonics of a peak elsewhere:
-    # suppression across slices, then refills.
+    # suppression across slices, then rescans.
     per = np.geomspace(0.5, 40.0, m)
     sr = rng.uniform(0.0, 1.0, m)
     top = 5 + 256 * np.arange(20)

@@ -378,7 +378,7 @@ def test_detection_crafted_periodograms(bls):
     """GPU detection of crafted SR arrays (float32, as the search writes
     them) equals the oracle's detection of the same values: peak indices
     bit-exact, statistics to FP64 rounding.  The cases drive the kernel's
-    candidate lists through refills, cross-slice suppression, ties and the
+    candidate buckets through rescans, cross-slice suppression, ties and the
     early stop."""
     import torch
     cases = synth.detection_periodograms()
