@@ -79,7 +79,7 @@ def test_sde_affine_invariance(a, c):
     assert d1["peak_index"].tolist() == d2["peak_index"].tolist()
 
 
-def test_crafted_refill_case_crowds_one_slice():
+def test_crafted_case_crowds_one_slice():
     """The first crafted detection case is what it claims: all 16 peaks
     (the 24 raised values, window too small to suppress) sit at indices
     3 mod 256, one thread slice of a 256-wide workgroup."""
