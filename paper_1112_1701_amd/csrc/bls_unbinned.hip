@@ -19,7 +19,10 @@ namespace {
 // comparison sort: a counting sort on a fine phase grid (about one point per
 // cell) groups the points, and each point's rank is its cell's start plus
 // the number of cell mates that precede it.  Sums over a run are exact:
-// FP64 sums of the integer fixed-point values of the prep pass, below 2^53.
+// differences of FP64 prefix sums of the integer fixed-point values of the
+// prep pass, all below 2^53.  Runs are screened eight ends at a time by a
+// bound from the prefix sums' extremes over those ends; only windows that
+// can hold the best run are scored run by run.
 
 __host__ __device__ inline int pow2_at_least(int n) {
   int m = 1;
