@@ -326,8 +326,9 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
     // S = P(r + L - 1) - P(r - 1) and R = L (or the same difference of the
     // weight sums), exact, as above.  Runs are screened against theta, the
     // best value any lane of the workgroup has found so far in this period
-    // (s_theta, raised as lanes improve; the lanes' final bests go to
-    // s_vbits): a run with S^2 < theta (1 - 2^-20) R (W - R) can be neither
+    // (s_theta holds it relaxed, theta (1 - 2^-20), raised as lanes improve;
+    // the lanes' final bests go to s_vbits): a run with
+    // S^2 < theta (1 - 2^-20) R (W - R) can be neither
     // the best nor a tie of it.  The ends are taken kUnbRun at a time, and a
     // window of ends is screened as a whole first: S^2 is at most the
     // largest |S| over the window (from the window's prefix-sum bounds;
@@ -348,23 +349,35 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
       const int eEnd = r + lmax - 1;  // last end, unwrapped
       const double base = r == 0 ? 0.0 : Pq[r - 1];
       const double wbase = WEIGHTED ? (r == 0 ? 0.0 : Pw[r - 1]) : 0.0;
-      for (int e = r; e <= eEnd; e += kUnbRun) {
-        // theta as the other lanes have raised it so far (a relaxed read:
-        // any value it returns is a bound some run reached)
+      // Window bounds against base, and base less one cycle's total past
+      // the end of the order: every quantity but the float bound is an
+      // integer below 2^53, so up and dn, rounded, still bound S.
+      const double base_w = base - Tq;
+      double Ru = 1.0;  // R of the window's first end (unit weights)
+      const double Rend = (double)lmax;
+      for (int e = r; e <= eEnd; e += kUnbRun, Ru += (double)kUnbRun) {
+        // theta (already relaxed) as the other lanes have raised it so far
+        // (a relaxed read: any value it returns is one some run reached)
         const unsigned long long tb =
             __hip_atomic_load(&s_theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        thr = fmax(thr, __longlong_as_double((long long)tb) * (1.0 - 0x1p-20));
+        thr = fmax(thr, __longlong_as_double((long long)tb));
         const bool wr = e >= nk;
         const float2 mb = Mb[wr ? e - nk : e];
-        const double off = wr ? Tq : 0.0;
-        const double up = ((double)mb.x + off) - base;   // >= every S of the window
-        const double dn = base - ((double)mb.y + off);   // >= every -S
+        const double bb = wr ? base_w : base;
+        const double up = (double)mb.x - bb;  // >= every S of the window
+        const double dn = bb - (double)mb.y;  // >= every -S
         const double sm = DIP ? fmax(dn, 0.0) : fmax(fmax(up, dn), 0.0);
-        const int eL = min(e + kUnbRun - 1, eEnd);
-        const double R1 = WEIGHTED ? pw_at(e) - wbase : (double)(e - r + 1);
-        const double R2 = WEIGHTED ? pw_at(eL) - wbase : (double)(eL - r + 1);
+        double R1, R2;
+        if (WEIGHTED) {
+          R1 = pw_at(e) - wbase;
+          R2 = pw_at(min(e + kUnbRun - 1, eEnd)) - wbase;
+        } else {
+          R1 = Ru;
+          R2 = fmin(Ru + (double)(kUnbRun - 1), Rend);
+        }
         const double g = fmin(R1 * (Wd - R1), R2 * (Wd - R2));
         if (!(sm * sm >= thr * g)) continue;
+        const int eL = min(e + kUnbRun - 1, eEnd);
         // The window's ends in two halves, each half's loads together.
         constexpr int kHalf = kUnbRun / 2;
 #pragma unroll
@@ -403,9 +416,9 @@ __global__ __launch_bounds__(kBlock) void unbinned_kernel(SearchArgs a) {
               btie = tie;
               bS = S;
               bR = R;
-              const double v = num / den;
-              thr = fmax(thr, v * (1.0 - 0x1p-20));
-              __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(v),
+              const double vr = num / den * (1.0 - 0x1p-20);  // relaxed
+              thr = fmax(thr, vr);
+              __hip_atomic_fetch_max(&s_theta, (unsigned long long)__double_as_longlong(vr),
                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
           }
