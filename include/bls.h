@@ -29,7 +29,10 @@
  * Precision: the phase is computed in FP64 with the operation order above,
  * so bins are those of an FP64 evaluation; per-bin sums are exact
  * fixed-point integers; box sums and the statistic are FP32.  SR agrees with
- * an FP64 evaluation to about 1e-6 relative.
+ * an FP64 evaluation to about 1e-6 relative.  Values and weights are encoded
+ * relative to the curve's largest |w y| and largest w (30 bits), so the error
+ * grows with the ratio of the largest value to the noise: within 1e-5 for a
+ * 1e4-sigma outlier, reaching 1e-5 near 1e5 sigma.
  *
  * Conventions: every function returns a bls_status.  No function throws.
  * Caller-owned host arrays are never retained after a synchronous call
