@@ -60,7 +60,9 @@ hipError_t device_alloc(void **ptr, size_t bytes) {
   const long long k = ++g_alloc_count;
   const char *hook = getenv("BLS_DEBUG_FAIL_ALLOC");
   if (hook && *hook) {
-    // "N": the N-th device allocation of the process fails; "all": every one.
+    // "N": the N-th device allocation of the process fails; "all": every one
+    // ("pinned" leaves device allocations alone and refuses the host-array
+    // path's pinned staging instead).
     if (strcmp(hook, "all") == 0 || atoll(hook) == k) return hipErrorOutOfMemory;
   }
   return hipMalloc(ptr, bytes > 0 ? bytes : 1);
@@ -810,6 +812,9 @@ void par_copy(void *dst, const void *src, size_t bytes) {
 // is not available (the host API then copies from pageable memory).
 bool ensure_host_stage(bls_plan *p) {
   if (p->h_stage) return true;
+  // BLS_DEBUG_FAIL_ALLOC=pinned: behave as if pinned memory were refused
+  const char *hook = getenv("BLS_DEBUG_FAIL_ALLOC");
+  if (hook && strcmp(hook, "pinned") == 0) return false;
   const size_t np = (size_t)p->cfg.max_points, nr = (size_t)p->cfg.max_periods,
                nc = (size_t)p->cfg.max_curves;
   const size_t in = 3 * np * 8 + nr * 8 + 256, res = 4 * nr * 4 + nc * 8 + 256;

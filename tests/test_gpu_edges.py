@@ -8,7 +8,8 @@
 * one long curve among hundreds of tiny ones in one persistent launch;
 * several device calls queued on one plan without synchronizing, each with
   its own batch;
-* the kernel-time ring, and the allocation-failure hook.
+* the kernel-time ring, and the allocation-failure hook;
+* the host-array path with and without its pinned staging.
 
 Every test prints the case it runs (flushed) before touching the GPU.
 """
@@ -298,3 +299,31 @@ def test_grouped_items_equal_tile_items(bls, monkeypatch, weighted):
         check_curve(lc, dict(sr=sr[lo:hi], depth=dp[lo:hi], jstart=js[lo:hi],
                              kwidth=ks[lo:hi], best_index=bi[k]), _orc(lc),
                     label="grouped %d" % k)
+
+
+def test_host_path_pageable_fallback(bls, monkeypatch):
+    """The host-array path without pinned staging (BLS_DEBUG_FAIL_ALLOC=pinned
+    refuses it) gives bit-identical results to the path with it, on a batch of
+    curves of different lengths and period grids."""
+    rng = np.random.default_rng(77)
+    curves = [synth.small_curve(7700 + k, int(n), nperiods=int(m), nbins=120,
+                                weighted=(k % 2 == 1))
+              for k, (n, m) in enumerate(zip(rng.integers(200, 3000, 5),
+                                             rng.integers(20, 200, 5)))]
+    _say("host path pageable fallback", [lc.n for lc in curves])
+    res = {}
+    for mode in ("pinned", "pageable"):
+        if mode == "pageable":
+            monkeypatch.setenv("BLS_DEBUG_FAIL_ALLOC", "pinned")
+        with bls.Plan(max_points=1 << 14, max_periods=1 << 12) as p:
+            res[mode] = [bls.bls_search(p.handle, lc.t, lc.x, lc.w, lc.periods,
+                                        lc.nbins, lc.qmin, lc.qmax)
+                         for lc in curves]
+        monkeypatch.delenv("BLS_DEBUG_FAIL_ALLOC", raising=False)
+    for k, (a, b) in enumerate(zip(res["pinned"], res["pageable"])):
+        for key in ("sr", "depth", "phase", "duration", "jstart", "kwidth"):
+            assert np.array_equal(a[key], b[key], equal_nan=True), (k, key)
+        assert a["best_index"] == b["best_index"], k
+    check_curve(curves[0], res["pageable"][0], _orc(curves[0]),
+                label="pageable host path")
+    assert "BLS_DEBUG_FAIL_ALLOC" not in os.environ
